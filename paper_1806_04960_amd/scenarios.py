@@ -1,0 +1,278 @@
+"""Seeded synthetic initial conditions for the explicit well-balanced step.
+
+This module produces *inputs only*: grids, parameters, solid masks and the initial state
+Q = (alpha rho, alpha rho u, alpha rho v, alpha) laid out as ``float64 [4, ny, nx]`` (x fastest).
+It holds none of the scheme's arithmetic; both the HIP library and the CPU oracle consume
+what it writes.
+
+Initial conditions follow the paper's test section (Sec. 5): two-level volume fraction
+(1 - eps in the liquid, eps in the gas, or 1 where a test says so), u = 0 and rho = rho0 in
+the gas, and in the liquid the water-at-rest density rho0 exp(-g rho0/k0 (y - y0(x)))
+(Sec. 5.5, same profile as Sec. 2.1), where y0(x) is the free surface of the rasterised liquid
+column.  A cell is solid / liquid iff its centre lies in the closed region.  The free-surface
+height of a column is written as (y_lo + n_solid dy) + dy * n_liquid, which is the value the
+free-surface detector returns for two-level alpha, so a liquid at rest starts exactly on the
+discrete equilibrium.  The exponential is evaluated with the C library's ``exp``
+(``math.exp``), the same routine the oracle calls.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+EPS = 1e-3      # alpha of the gas and 1 - alpha of the liquid (Sec. 5)
+CFL = 0.9       # CFL number of every workload
+RHO0 = 1000.0   # reference density (Sec. 5)
+GRAV = 9.81
+
+
+@dataclass
+class Scenario:
+    name: str
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    g: float = GRAV
+    k0: float = 6.54e5
+    rho0: float = RHO0
+    alpha_liq: float = 1.0 - EPS
+    alpha_gas: float = EPS
+    cfl: float = CFL
+    bc: tuple = (0, 0, 0, 0)          # W, E, S, N: 0 reflective, 1 transmissive
+    solid: np.ndarray | None = None   # uint8 [ny, nx], 1 = solid
+    q: np.ndarray | None = None       # float64 [4, ny, nx]
+    steps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y1 - self.y0) / self.ny
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def xc(self) -> np.ndarray:
+        return self.x0 + (np.arange(self.nx) + 0.5) * self.dx
+
+    def yc(self) -> np.ndarray:
+        return self.y0 + (np.arange(self.ny) + 0.5) * self.dy
+
+    def fluid(self) -> np.ndarray:
+        return np.ones((self.ny, self.nx), bool) if self.solid is None else self.solid == 0
+
+    def copy(self) -> "Scenario":
+        return replace(self, solid=None if self.solid is None else self.solid.copy(),
+                       q=None if self.q is None else self.q.copy(), meta=dict(self.meta))
+
+
+def _rect(s: Scenario, xa, xb, ya, yb) -> np.ndarray:
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    return (X >= xa) & (X <= xb) & (Y >= ya) & (Y <= yb)
+
+
+def _fill(s: Scenario, liquid: np.ndarray, u=None, v=None) -> Scenario:
+    """Two-level alpha, hydrostatic density in bottom-attached liquid columns, rho0 elsewhere."""
+    fluid = s.fluid()
+    liquid = liquid & fluid
+    alpha = np.where(liquid, s.alpha_liq, s.alpha_gas)
+    rho = np.full((s.ny, s.nx), s.rho0)
+    a = s.g * s.rho0 / s.k0
+    dy = s.dy
+    yc = s.yc()
+    for i in range(s.nx):
+        col_f = fluid[:, i]
+        jb = 0
+        while jb < s.ny and not col_f[jb]:
+            jb += 1
+        if np.any(~col_f[jb:]):
+            raise ValueError(f"column {i}: solid above fluid is not supported")
+        n_liq = int(liquid[:, i].sum())
+        y_surf = (s.y0 + jb * dy) + dy * float(n_liq)
+        for j in range(jb, s.ny):
+            if liquid[j, i]:
+                if not yc[j] < y_surf:
+                    raise ValueError(f"column {i}: liquid is not attached to the bottom")
+                rho[j, i] = s.rho0 * math.exp(-a * (yc[j] - y_surf))
+    q = np.zeros((4, s.ny, s.nx))
+    q[0] = alpha * rho
+    uu = np.zeros((s.ny, s.nx)) if u is None else np.where(liquid, u, 0.0)
+    vv = np.zeros((s.ny, s.nx)) if v is None else np.where(liquid, v, 0.0)
+    q[1] = q[0] * uu
+    q[2] = q[0] * vv
+    q[3] = alpha
+    # solid cells hold a benign gas state; they are never read by the scheme
+    gas = np.array([s.alpha_gas * s.rho0, 0.0, 0.0, s.alpha_gas])
+    q[:, ~fluid] = gas[:, None]
+    s.q = q
+    return s
+
+
+def _fill_free(s: Scenario, liquid: np.ndarray, u, v) -> Scenario:
+    """Liquid region not attached to the bottom (g = 0 tests): rho = rho0 everywhere."""
+    if s.g != 0.0:
+        raise ValueError("a floating liquid region needs g = 0")
+    fluid = s.fluid()
+    liquid = liquid & fluid
+    alpha = np.where(liquid, s.alpha_liq, s.alpha_gas)
+    q = np.zeros((4, s.ny, s.nx))
+    q[0] = alpha * s.rho0
+    q[1] = q[0] * np.where(liquid, u, 0.0)
+    q[2] = q[0] * np.where(liquid, v, 0.0)
+    q[3] = alpha
+    s.q = q
+    return s
+
+
+# ---------------------------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------------------------
+
+def rest_with_obstacle(nx: int = 128, ny: int = 64) -> Scenario:
+    """Water at rest in a closed 2 m x 1 m tank: liquid (alpha = 1) below y = 0.5 around a
+    rectangular obstacle [0.8, 1.2] x [0, 0.3], gas (alpha = 1e-3) above.  k0 = 2.78e5 (the
+    paper's equilibrium test, Sec. 5.1)."""
+    s = Scenario("rest_obstacle", nx, ny, 0.0, 2.0, 0.0, 1.0, k0=2.78e5, alpha_liq=1.0, cfl=CFL,
+                 steps=200)
+    s.solid = _rect(s, 0.8, 1.2, 0.0, 0.3).astype(np.uint8)
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    return _fill(s, Y < 0.5)
+
+
+def rest_flat(nx: int = 128, ny: int = 64) -> Scenario:
+    s = Scenario("rest_flat", nx, ny, 0.0, 2.0, 0.0, 1.0, k0=2.78e5, alpha_liq=1.0, cfl=CFL,
+                 steps=200)
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    return _fill(s, Y < 0.5)
+
+
+def dam_break_small(nx: int = 128, ny: int = 64) -> Scenario:
+    """128 x 64 dam break in a closed 2 m x 1 m tank, liquid column 0.5 m x 0.5 m in the left
+    corner, alpha = 1 - eps in the liquid (Sec. 3.4), k0 = 2.78e5."""
+    s = Scenario("dam_break_small", nx, ny, 0.0, 2.0, 0.0, 1.0, k0=2.78e5, steps=200)
+    return _fill(s, _rect(s, 0.0, 0.5, 0.0, 0.5))
+
+
+def dam_break(seed: int = 0, nx: int = 2048, ny: int = 1024) -> Scenario:
+    """Dam break with an obstacle on a 4 m x 2 m closed tank (headline workload at 2048 x 1024).
+    Column width W ~ U[0.8, 1.2], height H ~ U[0.5, 1.0] at the left wall; obstacle
+    [3.0, 3.1] x [0, h], h ~ U[0.05, 0.2]; k0 = 6.54e5 (the M = 0.3 value of Sec. 5.5/5.6)."""
+    rng = np.random.default_rng(seed)
+    W, H, h = rng.uniform(0.8, 1.2), rng.uniform(0.5, 1.0), rng.uniform(0.05, 0.2)
+    s = Scenario("dam_break", nx, ny, 0.0, 4.0, 0.0, 2.0, k0=6.54e5, steps=2000,
+                 meta={"seed": seed, "W": W, "H": H, "h_obstacle": h})
+    s.solid = _rect(s, 3.0, 3.1, 0.0, h).astype(np.uint8)
+    return _fill(s, _rect(s, 0.0, W, 0.0, H))
+
+
+def elliptic_drop(seed: int = 0, nx: int = 4096, ny: int = 4096) -> Scenario:
+    """Oscillating elliptical drop without gravity on [-1, 1]^2 (Sec. 5.2 set-up, rescaled):
+    semi-axes 0.5 (1 + da) along x and 0.25 (1 + db) along y, d ~ U[-0.02, 0.02];
+    u = -100 x, v = 100 y in the liquid, rho = rho0, k0 = 2.25e9 (c = 1500 m/s)."""
+    rng = np.random.default_rng(seed)
+    da, db = rng.uniform(-0.02, 0.02, size=2)
+    a, b = 0.5 * (1 + da), 0.25 * (1 + db)
+    s = Scenario("elliptic_drop", nx, ny, -1.0, 1.0, -1.0, 1.0, g=0.0, k0=2.25e9, steps=1000,
+                 meta={"seed": seed, "a": a, "b": b})
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    liquid = (X / a) ** 2 + (Y / b) ** 2 <= 1.0
+    return _fill_free(s, liquid, -100.0 * X, 100.0 * Y)
+
+
+def circular_drop(nx: int = 100, ny: int = 100, radius: float = 1.0, half_width: float = 3.0) -> Scenario:
+    """The paper's drop (Sec. 5.2): circle r = 1 in [-3, 3]^2, u = (-100 x, 100 y), g = 0,
+    k0 = 2.25e9, alpha = 1 - eps."""
+    s = Scenario("circular_drop", nx, ny, -half_width, half_width, -half_width, half_width, g=0.0,
+                 k0=2.25e9)
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    return _fill_free(s, X ** 2 + Y ** 2 <= radius ** 2, -100.0 * X, 100.0 * Y)
+
+
+def equilibrium_box(obstacle: bool, nx: int = 100, ny: int = 100) -> Scenario:
+    """Sec. 5.1: [-0.5, 0.5] x [0, 1] full of liquid (alpha = 1), k0 = 2.78e5, optionally
+    minus the obstacle [-0.25, 0.25] x [0, 0.33]."""
+    s = Scenario("equilibrium_obstacle" if obstacle else "equilibrium_flat", nx, ny, -0.5, 0.5, 0.0, 1.0,
+                 k0=2.78e5, alpha_liq=1.0, cfl=CFL)
+    if obstacle:
+        s.solid = _rect(s, -0.25, 0.25, 0.0, 0.33).astype(np.uint8)
+    return _fill(s, np.ones((ny, nx), bool))
+
+
+def ensemble(seed: int = 0, count: int = 64):
+    """Batch of uneven dam breaks on a 4 m x 2 m tank: sizes drawn from {256x128, 512x256,
+    768x384, 1024x512}; H ~ U[0.3, 1.0], W ~ U[0.3, 1.2]; 0-2 obstacles 0.1 m wide at
+    x ~ U[W + 0.2, 3.8] with heights U[0.05, 0.3]; k0 = 6.54e5; 500 steps each."""
+    rng = np.random.default_rng(seed)
+    sizes = [(256, 128), (512, 256), (768, 384), (1024, 512)]
+    out = []
+    for k in range(count):
+        nx, ny = sizes[int(rng.integers(0, 4))]
+        H, W = rng.uniform(0.3, 1.0), rng.uniform(0.3, 1.2)
+        n_obs = int(rng.integers(0, 3))
+        s = Scenario(f"ensemble_{k}", nx, ny, 0.0, 4.0, 0.0, 2.0, k0=6.54e5, steps=500,
+                     meta={"seed": seed, "member": k, "H": H, "W": W})
+        solid = np.zeros((ny, nx), bool)
+        for o in range(n_obs):
+            xo, ho = rng.uniform(W + 0.2, 3.8), rng.uniform(0.05, 0.3)
+            solid |= _rect(s, xo, xo + 0.1, 0.0, ho)
+        s.solid = solid.astype(np.uint8) if solid.any() else None
+        out.append(_fill(s, _rect(s, 0.0, W, 0.0, H)))
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Small cases for the oracle's pins and the parity tests
+# ---------------------------------------------------------------------------------------------
+
+def uniform_tank(nx: int, ny: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0, *, g=0.0, k0=2.78e5,
+                 alpha=1.0, alpha_liq=1.0, alpha_gas=EPS, bc=(0, 0, 0, 0), rho=None, u=None,
+                 v=None) -> Scenario:
+    """A box full of one phase with prescribed primitive fields (arrays [ny, nx] or scalars)."""
+    s = Scenario("uniform_tank", nx, ny, x0, x1, y0, y1, g=g, k0=k0, alpha_liq=alpha_liq,
+                 alpha_gas=alpha_gas, bc=tuple(bc))
+    shape = (ny, nx)
+    al = np.broadcast_to(np.asarray(alpha, float), shape)
+    r = np.broadcast_to(np.asarray(RHO0 if rho is None else rho, float), shape)
+    uu = np.broadcast_to(np.asarray(0.0 if u is None else u, float), shape)
+    vv = np.broadcast_to(np.asarray(0.0 if v is None else v, float), shape)
+    q = np.zeros((4, ny, nx))
+    q[0] = al * r
+    q[1] = q[0] * uu
+    q[2] = q[0] * vv
+    q[3] = al
+    s.q = q
+    return s
+
+
+def random_state(s: Scenario, seed: int, amp: float = 0.05, vel: float = 3.0) -> Scenario:
+    """Perturb a scenario's fluid cells with seeded noise (parity of generic, non-equilibrium
+    states): rho by +-amp relative, velocities by +-vel m/s in the liquid, alpha unchanged."""
+    rng = np.random.default_rng(seed)
+    q = s.q.copy()
+    fluid = s.fluid()
+    alpha = q[3]
+    rho = q[0] / alpha
+    rho = rho * (1.0 + amp * rng.uniform(-1, 1, rho.shape))
+    liq = alpha > 10 * s.alpha_gas
+    u = np.where(liq, vel * rng.uniform(-1, 1, rho.shape), 0.0)
+    v = np.where(liq, vel * rng.uniform(-1, 1, rho.shape), 0.0)
+    q[0] = np.where(fluid, alpha * rho, q[0])
+    q[1] = np.where(fluid, q[0] * u, q[1])
+    q[2] = np.where(fluid, q[0] * v, q[2])
+    out = s.copy()
+    out.q = q
+    out.name = s.name + f"_noise{seed}"
+    return out
+
+
+def scaled(builder, nx: int, ny: int, **kw) -> Scenario:
+    return builder(nx=nx, ny=ny, **kw)
