@@ -1,0 +1,110 @@
+/*
+ * bn2d.h -- C ABI of the MI355X (gfx950) library for the explicit time step of the
+ * second-order, well-balanced, path-conservative finite-volume scheme for the reduced
+ * three-equation Baer-Nunziato free-surface model (Gaburro, Castro, Dumbser,
+ * arXiv:1806.04960).
+ *
+ * State.  Q = (alpha rho, alpha rho u, alpha rho v, alpha) of the reduced model (Sec. 2,
+ * conservative variables of the non-conservative form; the gravity potential y of Sec. 2.1 is
+ * implicit: cell-centre and edge heights are computed from the grid).  A state buffer is
+ * 4 * nx * ny FP64 values in structure-of-arrays order: plane k (k = 0..3) then row j
+ * (0..ny-1, bottom to top) then column i (0..nx-1, x fastest).  Cell (i, j) covers
+ * [x0 + i dx, x0 + (i+1) dx] x [y0 + j dy, y0 + (j+1) dy], dx = (x1-x0)/nx, dy = (y1-y0)/ny
+ * (Sec. 3, Cartesian mesh).
+ *
+ * Ownership.  The context owns every device buffer it uses: two state buffers (ping-pong),
+ * the solid mask, the free-surface heights, the reduction scratch, dt and the elapsed time.
+ * State crosses the boundary only through bn_set_state / bn_get_state, which copy from / to
+ * a caller-owned device buffer.  All work is enqueued on the HIP stream given at creation
+ * (NULL = the legacy default stream); a context is used by one host thread at a time.
+ *
+ * Errors.  Every call returns BN_OK (0) or a negative BN_E* code; bn_strerror names it.
+ * Nothing is thrown across the ABI.  Asynchronous calls (bn_step, bn_run) report HIP launch
+ * errors immediately; non-physical states found on the device (a fluid cell with
+ * alpha rho <= 0, alpha <= 0 or a non-finite value) are reported by the next synchronising
+ * call (bn_compute_dt, bn_get_time, bn_status).  The product path has no CPU fallback.
+ */
+#ifndef BN2D_H
+#define BN2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BN_OK 0
+#define BN_EINVAL (-1)        /* bad argument: null pointer, size, parameter out of range */
+#define BN_EHIP (-2)          /* a HIP runtime call failed (text via bn_strerror) */
+#define BN_ENONPHYS (-3)      /* a fluid cell left the admissible set */
+#define BN_EUNSUPPORTED (-4)  /* a solid cell above a fluid cell in one column */
+#define BN_ENOMEM (-5)        /* device allocation failed */
+
+/* Cartesian grid of nx x ny cells on [x0, x1] x [y0, y1] (Sec. 3). */
+typedef struct {
+    int32_t nx, ny;
+    double x0, x1, y0, y1;
+} bn_grid;
+
+/* Model constants: gravity g (Sec. 2), Tait constants k0, rho0 with gamma = 1 (Sec. 2, all
+ * tests of Sec. 5), two-level volume fractions alpha_liq (liquid, 1 - eps or 1) and
+ * alpha_gas (eps) of the equilibrium profile and of the second-order switch alpha > 10 eps
+ * (Sec. 3.4), the CFL number, and the boundary condition of each side (W, E, S, N):
+ * 0 = reflective wall (mirror state with negated normal velocity, Sec. 5), 1 = transmissive.
+ * Requires k0 > 0, rho0 > 0, 0 < alpha_gas < alpha_liq <= 1, 0 < cfl <= 1, g >= 0. */
+typedef struct {
+    double g, k0, rho0, alpha_liq, alpha_gas, cfl;
+    int32_t bc[4];
+} bn_params;
+
+typedef struct bn_ctx bn_ctx;
+
+/* Create a context.  solid: host array of nx*ny bytes (row-major, 1 = solid cell removed from
+ * the domain, Sec. 5.1) or NULL; each column's solid cells must form one run attached to the
+ * bottom (else BN_EUNSUPPORTED), as the free-surface detector of Sec. 3.5 integrates alpha
+ * from the top of that run.  hip_stream: a hipStream_t or NULL.  Synchronous. */
+int bn_create(const bn_grid *grid, const bn_params *params, const uint8_t *solid, void *hip_stream,
+              bn_ctx **out);
+
+/* Copy a state from the caller's device buffer q_dev (4*nx*ny doubles, layout above) and
+ * compute its free-surface heights (Sec. 3.5) and CFL time step.  Stream-ordered. */
+int bn_set_state(bn_ctx *ctx, const double *q_dev);
+
+/* Copy the current state into the caller's device buffer q_dev.  Stream-ordered. */
+int bn_get_state(bn_ctx *ctx, double *q_dev);
+
+/* dt = CFL / max over fluid cells of ((|u|+c)/dx + (|v|+c)/dy) for the current state.
+ * Synchronises the stream; BN_ENONPHYS if the state is not admissible. */
+int bn_compute_dt(bn_ctx *ctx, double *dt_host);
+
+/* One explicit step of the scheme (Sec. 3, eq. Scheme) with the given dt > 0: free-surface
+ * detection, well-balanced reconstruction with Hancock predictor (Sec. 3.4), Osher edge
+ * fluctuations in x (Sec. 3.2), well-balanced Osher-Romberg fluctuations in y (Sec. 3.3), cell
+ * update.  Asynchronous on the context's stream; adds dt to the elapsed time. */
+int bn_step(bn_ctx *ctx, double dt);
+
+/* n_steps >= 0 steps, each with the CFL time step of the state it starts from, computed and
+ * kept on the device.  Asynchronous. */
+int bn_run(bn_ctx *ctx, int32_t n_steps);
+
+/* Elapsed simulated time since bn_set_state and the dt the next bn_run step will use.
+ * Synchronises; BN_ENONPHYS if a non-physical state was met. */
+int bn_get_time(bn_ctx *ctx, double *t_host, double *next_dt_host);
+
+/* Free-surface height of every column of the current state (nx doubles, host).  Synchronises. */
+int bn_get_y0(bn_ctx *ctx, double *y0_host);
+
+/* Synchronise and report BN_ENONPHYS if any step met a non-physical state. */
+int bn_status(bn_ctx *ctx);
+
+/* Rows each wavefront marches through per launch (tuning; default 16, range 1..4096). */
+int bn_set_rows_per_block(bn_ctx *ctx, int32_t rows);
+
+void bn_destroy(bn_ctx *ctx);
+const char *bn_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BN2D_H */

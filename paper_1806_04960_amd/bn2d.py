@@ -1,0 +1,170 @@
+"""ctypes binding of ``libbn2d.so`` (C ABI in ``include/bn2d.h``).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels.  Device memory and
+streams come from PyTorch (ROCm); states are ``torch.float64`` CUDA tensors of shape
+``[4, ny, nx]``.  There is no CPU fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbn2d.so")
+
+BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM = 0, -1, -2, -3, -4, -5
+
+SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
+           "bn_get_time", "bn_get_y0", "bn_status", "bn_set_rows_per_block", "bn_destroy", "bn_strerror")
+
+
+class BnError(RuntimeError):
+    def __init__(self, code: int, where: str, text: str):
+        super().__init__(f"{where}: {text} (code {code})")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("k0", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("alpha_liq", ctypes.c_double), ("alpha_gas", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("bc", ctypes.c_int32 * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1806_04960_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.bn_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint8), vp,
+                                ctypes.POINTER(vp)]
+        L.bn_set_state.argtypes = [vp, vp]
+        L.bn_get_state.argtypes = [vp, vp]
+        L.bn_compute_dt.argtypes = [vp, dp]
+        L.bn_step.argtypes = [vp, ctypes.c_double]
+        L.bn_run.argtypes = [vp, ctypes.c_int32]
+        L.bn_get_time.argtypes = [vp, dp, dp]
+        L.bn_get_y0.argtypes = [vp, dp]
+        L.bn_status.argtypes = [vp]
+        L.bn_set_rows_per_block.argtypes = [vp, ctypes.c_int32]
+        L.bn_destroy.argtypes = [vp]
+        L.bn_destroy.restype = None
+        L.bn_strerror.argtypes = [ctypes.c_int]
+        L.bn_strerror.restype = ctypes.c_char_p
+        for name in SYMBOLS:
+            if name not in ("bn_destroy", "bn_strerror"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str):
+    if code != BN_OK:
+        raise BnError(code, where, lib().bn_strerror(code).decode())
+
+
+def grid_of(s) -> Grid:
+    return Grid(int(s.nx), int(s.ny), float(s.x0), float(s.x1), float(s.y0), float(s.y1))
+
+
+def params_of(s) -> Params:
+    return Params(float(s.g), float(s.k0), float(s.rho0), float(s.alpha_liq), float(s.alpha_gas),
+                  float(s.cfl), (ctypes.c_int32 * 4)(*[int(b) for b in s.bc]))
+
+
+class Simulation:
+    """One context of the library on the current CUDA (HIP) device and stream.
+
+    ``scenario`` provides the grid (nx, ny, x0, x1, y0, y1), the parameters (g, k0, rho0,
+    alpha_liq, alpha_gas, cfl, bc) and the solid mask (uint8 [ny, nx] or None)."""
+
+    def __init__(self, scenario, stream=None, rows_per_block: int | None = None):
+        import numpy as np
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self.nx, self.ny = int(scenario.nx), int(scenario.ny)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        solid = None
+        self._solid_keep = None
+        if getattr(scenario, "solid", None) is not None:
+            self._solid_keep = np.ascontiguousarray(scenario.solid, dtype=np.uint8)
+            solid = self._solid_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        ctx = ctypes.c_void_p()
+        check(lib().bn_create(ctypes.byref(grid_of(scenario)), ctypes.byref(params_of(scenario)), solid,
+                              ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)), "bn_create")
+        self._ctx = ctx
+        if rows_per_block is not None:
+            check(lib().bn_set_rows_per_block(self._ctx, int(rows_per_block)), "bn_set_rows_per_block")
+
+    # -- state -------------------------------------------------------------------------------
+    def set_state(self, q):
+        import torch
+        if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous()
+                and tuple(q.shape) == (4, self.ny, self.nx)):
+            raise ValueError("state must be a contiguous float64 CUDA tensor of shape [4, ny, nx]")
+        check(lib().bn_set_state(self._ctx, ctypes.c_void_p(q.data_ptr())), "bn_set_state")
+
+    def get_state(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        check(lib().bn_get_state(self._ctx, ctypes.c_void_p(out.data_ptr())), "bn_get_state")
+        return out
+
+    # -- time stepping -------------------------------------------------------------------------
+    def compute_dt(self) -> float:
+        dt = ctypes.c_double()
+        check(lib().bn_compute_dt(self._ctx, ctypes.byref(dt)), "bn_compute_dt")
+        return dt.value
+
+    def step(self, dt: float):
+        check(lib().bn_step(self._ctx, float(dt)), "bn_step")
+
+    def run(self, n_steps: int):
+        check(lib().bn_run(self._ctx, int(n_steps)), "bn_run")
+
+    def time(self):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        check(lib().bn_get_time(self._ctx, ctypes.byref(t), ctypes.byref(dt)), "bn_get_time")
+        return t.value, dt.value
+
+    def y0(self):
+        import numpy as np
+        out = np.zeros(self.nx)
+        check(lib().bn_get_y0(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "bn_get_y0")
+        return out
+
+    def status(self):
+        check(lib().bn_status(self._ctx), "bn_status")
+
+    def set_rows_per_block(self, rows: int):
+        check(lib().bn_set_rows_per_block(self._ctx, int(rows)), "bn_set_rows_per_block")
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().bn_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

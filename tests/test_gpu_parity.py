@@ -1,0 +1,209 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle, element by element.
+
+Tolerance (max relative error 1e-11 on all state fields): per field k,
+    e_k = max |Q_k^gpu - Q_k^oracle| / max(max |Q_k^oracle|, s_k),
+s = (rho0 alpha_l, rho0 c alpha_l, rho0 c alpha_l, 1): the momenta are normalised by the
+acoustic momentum scale because they are zero at rest.  Both sides take the same readings of the
+paper; they differ in rounding only (closed-form 4 x 4 eigen-actions against printed 5 x 5 matrices,
+factored exponentials, FMA contraction), and the step is Lipschitz in its input, so rounding
+differences stay at rounding size over the stated step counts.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1806_04960_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def field_errors(s, q_gpu, q_ref):
+    c = math.sqrt(s.k0 / s.rho0)
+    scales = [s.rho0 * s.alpha_liq, s.rho0 * c * s.alpha_liq, s.rho0 * c * s.alpha_liq, 1.0]
+    errs = []
+    for k in range(4):
+        denom = max(np.abs(q_ref[k]).max(), scales[k])
+        errs.append(np.abs(q_gpu[k] - q_ref[k]).max() / denom)
+    return np.array(errs)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bn(torch_cuda):
+    from paper_1806_04960_amd import bn2d
+    bn2d.lib()
+    return bn2d
+
+
+def gpu_run(bn, torch, s, n_steps, rows=None, q0=None):
+    q0 = s.q if q0 is None else q0
+    with bn.Simulation(s, rows_per_block=rows) as sim:
+        sim.set_state(torch.from_numpy(np.ascontiguousarray(q0)).cuda())
+        sim.run(n_steps)
+        t, dt_next = sim.time()
+        q = sim.get_state().cpu().numpy()
+        y0 = sim.y0()
+    return q, t, dt_next, y0
+
+
+def assert_parity(s, q_gpu, q_ref, tol=TOL):
+    e = field_errors(s, q_gpu, q_ref)
+    print(f"{s.name}: field errors {e}", flush=True)
+    assert np.all(e <= tol), e
+
+
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("builder", [sc.rest_with_obstacle, sc.rest_flat])
+def test_rest_200_steps(oracle, bn, torch_cuda, builder):
+    s = builder()
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 200)
+    qo, to, dto = oracle.run(s, s.q, 200)
+    assert_parity(s, qg, qo)
+    assert abs(tg - to) <= 1e-12 * to
+    np.testing.assert_allclose(y0g, oracle.detector(s, qo), rtol=0, atol=1e-14)
+
+
+def test_rest_with_obstacle_1000_steps_kept_to_round_off(oracle, bn, torch_cuda):
+    s = sc.rest_with_obstacle()
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 1000)
+    fl = s.fluid()
+    assert np.abs(qg[1] / qg[0])[fl].max() < 1e-11
+    assert np.abs(qg[2] / qg[0])[fl].max() < 1e-11
+    assert np.abs(qg[0] - s.q[0])[fl].max() / s.rho0 < 1e-12
+    qo, to, dto = oracle.run(s, s.q, 1000)
+    assert_parity(s, qg, qo)
+
+
+def test_dam_break_200_steps(oracle, bn, torch_cuda):
+    s = sc.dam_break_small()
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 200)
+    qo, to, dto = oracle.run(s, s.q, 200)
+    assert_parity(s, qg, qo)
+    assert abs(tg - to) <= 1e-11 * to
+    lam, dt_o = oracle.cfl(s, qo)
+    assert abs(dtg - dt_o) <= 1e-11 * dt_o
+
+
+@pytest.mark.parametrize("rows", [1, 3, 7, 16, 64])
+def test_ragged_grid_tilings(oracle, bn, torch_cuda, rows):
+    """Sizes that are not multiples of the 60-column strip or the row block, an obstacle,
+    a noisy non-equilibrium state; every row-block height."""
+    s = sc.random_state(sc.dam_break(7, 67, 37), seed=3, amp=0.01, vel=0.5)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 25, rows=rows)
+    qo, to, dto = oracle.run(s, s.q, 25)
+    assert_parity(s, qg, qo)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 40), (40, 1), (2, 2), (1, 1), (61, 5), (121, 3)])
+def test_degenerate_shapes(oracle, bn, torch_cuda, nx, ny):
+    s = sc.random_state(sc.dam_break_small(nx, ny), seed=nx * 100 + ny, amp=0.005, vel=0.3)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 10)
+    qo, to, dto = oracle.run(s, s.q, 10)
+    assert_parity(s, qg, qo)
+
+
+def test_transmissive_boundaries(oracle, bn, torch_cuda):
+    s = sc.dam_break_small(64, 32)
+    s.bc = (1, 1, 0, 1)
+    s = sc.random_state(s, seed=11, amp=0.01, vel=1.0)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 40)
+    qo, to, dto = oracle.run(s, s.q, 40)
+    assert_parity(s, qg, qo)
+
+
+def test_explicit_dt_steps(oracle, bn, torch_cuda):
+    import torch
+    s = sc.random_state(sc.dam_break(2, 50, 30), seed=4, amp=0.02, vel=1.0)
+    lam, dt = oracle.cfl(s, s.q)
+    q_ref = s.q.copy()
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch.from_numpy(s.q.copy()).cuda())
+        assert abs(sim.compute_dt() - dt) <= 1e-14 * dt
+        for k in range(3):
+            sim.step(0.5 * dt)
+            q_ref = oracle.step(s, q_ref, 0.5 * dt)
+        q = sim.get_state().cpu().numpy()
+        t, _ = sim.time()
+    assert_parity(s, q, q_ref)
+    assert t == pytest.approx(1.5 * dt, rel=1e-15)
+
+
+def test_drop_without_gravity(oracle, bn, torch_cuda):
+    s = sc.elliptic_drop(1, 96, 96)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 60)
+    qo, to, dto = oracle.run(s, s.q, 60)
+    assert_parity(s, qg, qo)
+
+
+def test_nonphysical_state_is_reported(bn, torch_cuda):
+    import torch
+    s = sc.dam_break_small(32, 16)
+    q = s.q.copy()
+    q[0, 3, 3] = -1.0
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch.from_numpy(q).cuda())
+        with pytest.raises(bn.BnError) as e:
+            sim.compute_dt()
+        assert e.value.code == bn.BN_ENONPHYS
+
+
+# ---------------------------------------------------------------------------------------------
+# Full-size workloads: one step from the generated state, checked on sampled cells, and
+# properties that hold at any size after the benchmark's launch configuration has run.
+# ---------------------------------------------------------------------------------------------
+
+def _sample_cells(s, n, seed):
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(s.nx * s.ny, size=n, replace=False)
+    # plus every cell of a band across the free surface / liquid front and the domain corners
+    extra = [0, s.nx - 1, s.nx * (s.ny - 1), s.nx * s.ny - 1]
+    return np.unique(np.concatenate([cells, extra]))
+
+
+@pytest.mark.parametrize("builder", [lambda: sc.dam_break(0), lambda: sc.elliptic_drop(0)])
+def test_full_size_first_step_on_sampled_cells(oracle, bn, torch_cuda, builder):
+    import torch
+    s = builder()
+    lam, dt = oracle.cfl(s, s.q)
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch.from_numpy(s.q).cuda())
+        sim.run(1)
+        q1 = sim.get_state().cpu().numpy()
+    cells = _sample_cells(s, 4000, 1)
+    # add cells next to the liquid boundary, where the scheme does the most work
+    alpha = s.q[3]
+    near = np.zeros(alpha.shape, bool)
+    near[:, :-1] |= np.abs(np.diff(alpha, axis=1)) > 0.1
+    near[:-1, :] |= np.abs(np.diff(alpha, axis=0)) > 0.1
+    edge = np.flatnonzero(near)
+    edge = edge[np.random.default_rng(2).permutation(edge.size)[:3000]]
+    cells = np.unique(np.concatenate([cells, edge]))
+    ref = oracle.step_cells(s, s.q, dt, cells)
+    got = q1.reshape(4, -1)[:, cells]
+    sub = s.copy()
+    assert_parity(sub, got, ref)
+
+
+def test_full_size_dam_break_conserves_mass_over_bench_steps(bn, torch_cuda):
+    import torch
+    s = sc.dam_break(0)
+    fl = s.fluid()
+    m0 = math.fsum(s.q[0][fl].ravel())
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch.from_numpy(s.q).cuda())
+        sim.run(200)
+        sim.status()
+        q = sim.get_state().cpu().numpy()
+    m1 = math.fsum(q[0][fl].ravel())
+    assert abs(m1 - m0) / m0 < 1e-12
+    assert q[3][fl].min() > 0 and q[3][fl].max() <= 1.0
