@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit well-balanced Osher-Romberg step on one MI355X.
+
+One step = one pass of the whole scheme over the grid: free-surface detection, reconstruction with
+predictor, every x- and y-edge fluctuation, cell update, CFL reduction.  Default workload: the
+2048 x 1024 dam break with an obstacle (seed 0), 2000 timed steps at CFL 0.9, state resident in HBM.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR = 78.6e12     # MI355X FP64 vector peak, FLOP/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E peak, B/s
+STATE_BYTES_PER_CELL = 64      # read 4 FP64 + write 4 FP64 per cell update
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_dam_break_2048x1024_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_04960_amd", "csrc", f)
+                  for f in ("bn2d_step.hip", "bn2d_physics.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; otherwise None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_workload(name):
+    from paper_1806_04960_amd import scenarios as sc
+    if name == "dam_break":
+        return sc.dam_break(0)
+    if name == "elliptic_drop":
+        return sc.elliptic_drop(0)
+    if name == "dam_break_small":
+        return sc.dam_break_small()
+    raise ValueError(name)
+
+
+def cpu_baseline(s, steps):
+    """The CPU oracle, single thread, on `steps` full steps of the same workload from its initial
+    state (a bounded sample of the timed run)."""
+    from oracle import bnref
+    q = s.q.copy()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lam, dt = bnref.cfl(s, q)
+        q = bnref.step(s, q, dt)
+    el = time.perf_counter() - t0
+    return {"value": s.nx * s.ny * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full oracle steps of the {s.nx}x{s.ny} {s.name} from its initial state "
+                      f"({el:.1f} s, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="dam_break", choices=["dam_break", "elliptic_drop", "dam_break_small"])
+    ap.add_argument("--rows", type=int, default=None, help="row-block height of the step kernel")
+    ap.add_argument("--cpu-baseline-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would own a strip "
+              "of columns; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1806_04960_amd import bn2d, flops
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    s = build_workload(args.workload)
+    print(f"# workload {s.name} {s.nx}x{s.ny}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+          flush=True)
+
+    q0 = torch.from_numpy(s.q).cuda()
+    with bn2d.Simulation(s, rows_per_block=args.rows) as sim:
+        sim.set_state(q0)
+        y0_start = sim.y0()
+        dt_start = sim.compute_dt()
+        sim.run(args.warmup)
+        sim.status()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        sim.run(args.steps)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        sim.status()
+        q_end = sim.get_state().cpu().numpy()
+        y0_end = sim.y0()
+        t_end, dt_end = sim.time()
+
+    cells = s.nx * s.ny
+    ms_per_step = ms / args.steps
+    value = cells * args.steps / (ms / 1e3)
+
+    # algorithmic FLOPs per launch: mean of the counts on the first and last state of the run
+    f0 = flops.count(s, s.q, y0_start, dt_start)
+    f1 = flops.count(s, q_end, y0_end, dt_end)
+    flops_per_launch = 0.5 * (f0["total"] + f1["total"])
+    achieved = flops_per_launch / (ms_per_step / 1e3)
+    traffic = measured_traffic()
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
+                "flops_per_cell_update": flops_per_launch / cells,
+                "hbm_frac_at_algorithmic_bytes": cells * STATE_BYTES_PER_CELL / (ms_per_step / 1e3) / PEAK_HBM}
+
+    line = {
+        "metric": "FP64 cell updates/sec",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name} {s.nx}x{s.ny} seed 0, CFL {s.cfl}", "nx": s.nx, "ny": s.ny,
+                   "cells": cells, "simulated_time_s": t_end},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline and args.cpu_baseline_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(s, args.cpu_baseline_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -21,156 +21,6 @@
 
 namespace bn {
 
-struct Rec {
-    double qW[4], qE[4], qS[4], qN[4];  // edge-midpoint states at t^{n+1/2}
-    double e1S, e1N, aE;                // equilibrium parts (alpha rho)^E, alpha^E of the S/N states
-    double yS, yN;                      // heights of the S/N states
-    double fdiff[4], gdiff[4];          // f(q_E) - f(q_W), g(q_N) - g(q_S)
-    double vol2, vol3;                  // cell integral of B(q) grad q (components 3 and 4)
-};
-
-// Well-balanced second-order reconstruction with Hancock predictor of the window centre
-// (Sec. 3.4): fluctuations of the 3 x 3 stencil with respect to the centre cell's water-at-rest
-// profile (Sec. 2.1, free surface y0c of its column), Barth-Jespersen limited central
-// gradients component by component, d_t Q = -(A1 d_x Q + A2 d_y Q) with grad Q = grad Q^E +
-// Psi grad Q^f.  Second order only if the centre and every fluid stencil cell hold liquid
-// (alpha > 10 alpha_gas); otherwise the first-order states of Sec. 3.2/3.3.
-__device__ __forceinline__ void reconstruct(const Consts &K, const double (&wq)[3][3][4], const int (&wf)[3][3],
-                                            int j, double y0c, double dt, Rec &r)
-{
-    const double *Qc = wq[1][1];
-    const double yc = K.ylo + (j + 0.5) * K.dy;
-    const bool liquid = yc < y0c;
-    const double aE = liquid ? K.al : K.ag;
-    const double rE0 = liquid ? K.rho0 * exp(-K.a * (yc - y0c)) : K.rho0;
-    const double e1c = aE * rE0;
-    r.aE = aE;
-
-    bool so = Qc[3] > K.so_thr;
-#pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-        for (int di = 0; di < 3; ++di)
-            if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > K.so_thr)) so = false;
-
-    if (!so) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            r.qW[k] = Qc[k]; r.qE[k] = Qc[k]; r.qS[k] = Qc[k]; r.qN[k] = Qc[k];
-            r.fdiff[k] = 0.0; r.gdiff[k] = 0.0;
-        }
-        r.e1S = e1c; r.e1N = e1c; r.yS = yc; r.yN = yc;
-        r.vol2 = 0.0; r.vol3 = 0.0;
-        return;
-    }
-
-    const double e1row[3] = {aE * (liquid ? rE0 * K.e_dn1 : K.rho0), e1c, aE * (liquid ? rE0 * K.e_up1 : K.rho0)};
-    const double fc[4] = {Qc[0] - e1c, Qc[1], Qc[2], Qc[3] - aE};
-
-    double phi[3][3][4];
-#pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-        for (int di = 0; di < 3; ++di) {
-            const int f = wf[dj][di];
-            if (f & F_FLUID) {
-                phi[dj][di][0] = wq[dj][di][0] - e1row[dj];
-                phi[dj][di][1] = wq[dj][di][1];
-                phi[dj][di][2] = wq[dj][di][2];
-                phi[dj][di][3] = wq[dj][di][3] - aE;
-            } else {
-                // mirror of the centre across each separating reflective wall
-                const bool outx = f & (F_OUTW | F_OUTE), outy = f & (F_OUTS | F_OUTN);
-                const bool inside = !outx && !outy;
-                const bool fx = (di != 1) && (inside || (outx && K.bc[(f & F_OUTW) ? 0 : 1] == 0));
-                const bool fy = (dj != 1) && (inside || (outy && K.bc[(f & F_OUTS) ? 2 : 3] == 0));
-                phi[dj][di][0] = fc[0];
-                phi[dj][di][1] = fx ? -fc[1] : fc[1];
-                phi[dj][di][2] = fy ? -fc[2] : fc[2];
-                phi[dj][di][3] = fc[3];
-            }
-        }
-
-    double gx[4], gy[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double gxr = (phi[1][2][k] - phi[1][0][k]) / (2.0 * K.dx);
-        const double gyr = (phi[2][1][k] - phi[0][1][k]) / (2.0 * K.dy);
-        double mx = phi[1][1][k], mn = phi[1][1][k];
-#pragma unroll
-        for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-            for (int di = 0; di < 3; ++di) {
-                mx = fmax(mx, phi[dj][di][k]);
-                mn = fmin(mn, phi[dj][di][k]);
-            }
-        // Barth-Jespersen over the four edge midpoints: the two x (y) midpoints carry +-d, so
-        // their ratios are (max - c)/|d| and (c - min)/|d|.
-        const double lim = fmin(mx - fc[k], fc[k] - mn);
-        const double hx = fabs(gxr * (0.5 * K.dx)), hy = fabs(gyr * (0.5 * K.dy));
-        const double px = hx > 0.0 ? fmin(1.0, lim / hx) : 1.0;
-        const double py = hy > 0.0 ? fmin(1.0, lim / hy) : 1.0;
-        const double psi = fmin(px, py);
-        gx[k] = psi * gxr;
-        gy[k] = psi * gyr;
-    }
-
-    // Hancock predictor with A1, A2 at the cell average (Sec. 3 matrices; rho c^2 - p = k0).
-    const double inv0 = 1.0 / Qc[0];
-    const double u = Qc[1] * inv0, v = Qc[2] * inv0;
-    const double qy0 = gy[0] + aE * (liquid ? -K.a * rE0 : 0.0);
-    double hdt[4];
-    {
-        const double ax0 = gx[1];
-        const double ax1 = (K.c2 - u * u) * gx[0] + 2.0 * u * gx[1] - K.k0 * gx[3];
-        const double ax2 = -u * v * gx[0] + v * gx[1] + u * gx[2];
-        const double ax3 = u * gx[3];
-        const double ay0 = gy[2];
-        const double ay1 = -u * v * qy0 + v * gy[1] + u * gy[2];
-        const double ay2 = (K.c2 - v * v) * qy0 + 2.0 * v * gy[2] - K.k0 * gy[3] + Qc[0] * K.g;
-        const double ay3 = v * gy[3];
-        const double h = -0.5 * dt;
-        hdt[0] = h * (ax0 + ay0);
-        hdt[1] = h * (ax1 + ay1);
-        hdt[2] = h * (ax2 + ay2);
-        hdt[3] = h * (ax3 + ay3);
-    }
-
-    const double e1S = aE * (liquid ? rE0 * K.e_dnh : K.rho0);
-    const double e1N = aE * (liquid ? rE0 * K.e_uph : K.rho0);
-    const double ex[4] = {e1c, 0.0, 0.0, aE}, eS[4] = {e1S, 0.0, 0.0, aE}, eN[4] = {e1N, 0.0, 0.0, aE};
-    const double hx = 0.5 * K.dx, hy = 0.5 * K.dy;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        r.qW[k] = (ex[k] + fc[k]) + gx[k] * (-hx) + hdt[k];
-        r.qE[k] = (ex[k] + fc[k]) + gx[k] * hx + hdt[k];
-        r.qS[k] = (eS[k] + fc[k]) + gy[k] * (-hy) + hdt[k];
-        r.qN[k] = (eN[k] + fc[k]) + gy[k] * hy + hdt[k];
-    }
-    r.e1S = e1S;
-    r.e1N = e1N;
-    r.yS = K.ylo + j * K.dy;
-    r.yN = K.ylo + (j + 1) * K.dy;
-
-    // Cell terms: the flux differences of the cell's own linear reconstruction and the midpoint
-    // rule for the cell integral of B(q) grad q at (x_c, t^{n+1/2}) (Sec. 3.4).
-    double fE[4], fW[4], gN[4], gS[4];
-    flux_f(K, r.qE, 1.0 / r.qE[0], fE);
-    flux_f(K, r.qW, 1.0 / r.qW[0], fW);
-    flux_g(r.qN, 1.0 / r.qN[0], gN);
-    flux_g(r.qS, 1.0 / r.qS[0], gS);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        r.fdiff[k] = fE[k] - fW[k];
-        r.gdiff[k] = gN[k] - gS[k];
-    }
-    const double qc0 = Qc[0] + hdt[0];
-    const double ic = 1.0 / qc0;
-    const double uc = (Qc[1] + hdt[1]) * ic, vc = (Qc[2] + hdt[2]) * ic;
-    r.vol2 = K.k0 * (gy[0] / K.rho0 - gy[3]) + (qc0 - e1c) * K.g;
-    r.vol3 = uc * gx[3] + vc * gy[3];
-}
-
 __device__ __forceinline__ double shfl_from_left(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double shfl_from_right(double v) { return __shfl_down(v, 1, 64); }
 __device__ __forceinline__ int shfl_from_left(int v) { return __shfl_up(v, 1, 64); }
@@ -192,7 +42,6 @@ __global__ __launch_bounds__(64) void step_kernel(const double *__restrict__ Q, 
     const double dt = dt_dev ? *dt_dev : dt_arg;
     const double dtdx = dt / K.dx, dtdy = dt / K.dy;
     const double y0c = colin ? Y0[i] : 0.0;
-    const double c = K.c;
 
     double wq[3][3][4];
     int wf[3][3];
@@ -316,16 +165,11 @@ __global__ __launch_bounds__(64) void step_kernel(const double *__restrict__ Q, 
             const int ff = wf[0][1];
             if (ff & F_FLUID) {
                 double qn[4];
-                qn[0] = pP[0] - dtdy * ((pDpS[0] + DyM[0]) + pG[0]);
-                qn[1] = pP[1] - dtdy * ((pDpS[1] + DyM[1]) + pG[1]);
-                qn[2] = pP[2] - dtdy * ((pDpS[2] + DyM[2]) + pG[2]) - dt * pV2;
-                qn[3] = pP[3] - dtdy * ((pDpS[3] + DyM[3]) + pG[3]) - dt * pV3;
+                update_finish(pP, pDpS, DyM, pG, pV2, pV3, dt, dtdy, qn);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) Qn[k * plane + cidx] = qn[k];
-                colsum += (qn[3] - K.ag) / (K.al - K.ag);
-                const double iq = 1.0 / qn[0];
-                const double uu = qn[1] * iq, vv = qn[2] * iq;
-                lam = fmax(lam, (fabs(uu) + c) / K.dx + (fabs(vv) + c) / K.dy);
+                colsum += detector_term(K, qn);
+                lam = fmax(lam, cfl_rate(K, qn));
                 if (!(qn[0] > 0.0) || !(qn[3] > 0.0) || !isfinite(qn[0]) || !isfinite(qn[1]) ||
                     !isfinite(qn[2]) || !isfinite(qn[3]))
                     bad = 1;
@@ -337,9 +181,9 @@ __global__ __launch_bounds__(64) void step_kernel(const double *__restrict__ Q, 
 
         // ---- row jr becomes the pending row ------------------------------------------------
         if (jr_inside_block && fl) {
+            update_x_part(wq[1][1], DpW, DmE, rc.fdiff, dtdx, pP);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                pP[k] = wq[1][1][k] - dtdx * ((DpW[k] + DmE[k]) + rc.fdiff[k]);
                 pDpS[k] = DyP[k];
                 pG[k] = rc.gdiff[k];
             }
@@ -384,9 +228,9 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
             const size_t cidx = (size_t)j * K.nx + i;
             if (solid && solid[cidx]) continue;
             const double q0 = Q[cidx], q1 = Q[plane + cidx], q2 = Q[2 * plane + cidx], q3 = Q[3 * plane + cidx];
-            colsum += (q3 - K.ag) / (K.al - K.ag);
-            const double iq = 1.0 / q0;
-            lam = fmax(lam, (fabs(q1 * iq) + K.c) / K.dx + (fabs(q2 * iq) + K.c) / K.dy);
+            const double q[4] = {q0, q1, q2, q3};
+            colsum += detector_term(K, q);
+            lam = fmax(lam, cfl_rate(K, q));
             if (!(q0 > 0.0) || !(q3 > 0.0) || !isfinite(q0) || !isfinite(q1) || !isfinite(q2) || !isfinite(q3))
                 bad = 1;
         }
