@@ -82,7 +82,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="dam_break", choices=["dam_break", "elliptic_drop", "dam_break_small"])
-    ap.add_argument("--rows", type=int, default=None, help="row-block height of the step kernel")
+    ap.add_argument("--rows", type=int, default=None, help="rows per claimed block of the step kernel")
+    ap.add_argument("--wavefronts", type=int, default=None, help="wavefronts of the persistent step kernel")
     ap.add_argument("--cpu-baseline-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -106,8 +107,9 @@ def main():
           flush=True)
 
     q0 = torch.from_numpy(s.q).cuda()
-    with bn2d.Simulation(s, rows_per_block=args.rows) as sim:
+    with bn2d.Simulation(s, rows_per_block=args.rows, wavefronts=args.wavefronts) as sim:
         sim.set_state(q0)
+        rows, waves = sim.launch()
         y0_start = sim.y0()
         dt_start = sim.compute_dt()
         sim.run(args.warmup)
@@ -153,7 +155,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{s.name} {s.nx}x{s.ny} seed 0, CFL {s.cfl}", "nx": s.nx, "ny": s.ny,
-                   "cells": cells, "simulated_time_s": t_end},
+                   "cells": cells, "simulated_time_s": t_end,
+                   "rows_per_block": rows, "wavefronts": waves},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline and args.cpu_baseline_steps > 0:

@@ -13,7 +13,8 @@
  * (Sec. 3, Cartesian mesh).
  *
  * Ownership.  The context owns every device buffer it uses: two state buffers (ping-pong),
- * the solid mask, the free-surface heights, the reduction scratch, dt and the elapsed time.
+ * the solid mask, the per-column free-surface integrals (64-bit fixed point), the step kernel's
+ * work lists, the CFL maximum, dt and the elapsed time.
  * State crosses the boundary only through bn_set_state / bn_get_state, which copy from / to
  * a caller-owned device buffer.  All work is enqueued on the HIP stream given at creation
  * (NULL = the legacy default stream); a context is used by one host thread at a time.
@@ -39,6 +40,7 @@ extern "C" {
 #define BN_ENONPHYS (-3)      /* a fluid cell left the admissible set */
 #define BN_EUNSUPPORTED (-4)  /* a solid cell above a fluid cell in one column */
 #define BN_ENOMEM (-5)        /* device allocation failed */
+#define BN_EINTERNAL (-6)     /* the step kernel's work distribution failed (a bug, never expected) */
 
 /* Cartesian grid of nx x ny cells on [x0, x1] x [y0, y1] (Sec. 3). */
 typedef struct {
@@ -97,8 +99,15 @@ int bn_get_y0(bn_ctx *ctx, double *y0_host);
 /* Synchronise and report BN_ENONPHYS if any step met a non-physical state. */
 int bn_status(bn_ctx *ctx);
 
-/* Rows each wavefront marches through per launch (tuning; default 16, range 1..4096). */
-int bn_set_rows_per_block(bn_ctx *ctx, int32_t rows);
+/* Launch shape of the step kernel.  Wavefronts march strips of 60 columns and claim rows in blocks
+ * of rows_per_block (1..4096, 0 = default 4); the launch is persistent with `wavefronts`
+ * wavefronts (1..65536, 0 = default: one per SIMD of the device).  Results are bitwise the same
+ * for every shape: each cell is computed by the same arithmetic whatever wavefront does it, and
+ * the free-surface integral is summed exactly (64-bit fixed point).  Synchronises the stream. */
+int bn_set_launch(bn_ctx *ctx, int32_t rows_per_block, int32_t wavefronts);
+
+/* The current launch shape (defaults resolved); either pointer may be NULL. */
+int bn_get_launch(bn_ctx *ctx, int32_t *rows_per_block, int32_t *wavefronts);
 
 void bn_destroy(bn_ctx *ctx);
 const char *bn_strerror(int code);

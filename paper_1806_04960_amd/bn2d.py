@@ -10,12 +10,14 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbn2d.so")
+# BN2D_LIB selects another build of the same ABI (e.g. to compare two kernel versions).
+LIB_PATH = os.environ.get("BN2D_LIB", os.path.join(HERE, "libbn2d.so"))
 
-BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM = 0, -1, -2, -3, -4, -5
+BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
-           "bn_get_time", "bn_get_y0", "bn_status", "bn_set_rows_per_block", "bn_destroy", "bn_strerror")
+           "bn_get_time", "bn_get_y0", "bn_status", "bn_set_launch", "bn_get_launch", "bn_destroy",
+           "bn_strerror")
 
 
 class BnError(RuntimeError):
@@ -56,7 +58,8 @@ def lib():
         L.bn_get_time.argtypes = [vp, dp, dp]
         L.bn_get_y0.argtypes = [vp, dp]
         L.bn_status.argtypes = [vp]
-        L.bn_set_rows_per_block.argtypes = [vp, ctypes.c_int32]
+        L.bn_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.bn_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.bn_destroy.argtypes = [vp]
         L.bn_destroy.restype = None
         L.bn_strerror.argtypes = [ctypes.c_int]
@@ -88,7 +91,7 @@ class Simulation:
     ``scenario`` provides the grid (nx, ny, x0, x1, y0, y1), the parameters (g, k0, rho0,
     alpha_liq, alpha_gas, cfl, bc) and the solid mask (uint8 [ny, nx] or None)."""
 
-    def __init__(self, scenario, stream=None, rows_per_block: int | None = None):
+    def __init__(self, scenario, stream=None, rows_per_block: int | None = None, wavefronts: int | None = None):
         import numpy as np
         import torch
 
@@ -105,8 +108,8 @@ class Simulation:
         check(lib().bn_create(ctypes.byref(grid_of(scenario)), ctypes.byref(params_of(scenario)), solid,
                               ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)), "bn_create")
         self._ctx = ctx
-        if rows_per_block is not None:
-            check(lib().bn_set_rows_per_block(self._ctx, int(rows_per_block)), "bn_set_rows_per_block")
+        if rows_per_block is not None or wavefronts is not None:
+            self.set_launch(rows_per_block or 0, wavefronts or 0)
 
     # -- state -------------------------------------------------------------------------------
     def set_state(self, q):
@@ -149,8 +152,15 @@ class Simulation:
     def status(self):
         check(lib().bn_status(self._ctx), "bn_status")
 
-    def set_rows_per_block(self, rows: int):
-        check(lib().bn_set_rows_per_block(self._ctx, int(rows)), "bn_set_rows_per_block")
+    def set_launch(self, rows_per_block: int = 0, wavefronts: int = 0):
+        """Launch shape of the step kernel (0 = default for either)."""
+        check(lib().bn_set_launch(self._ctx, int(rows_per_block), int(wavefronts)), "bn_set_launch")
+
+    def launch(self):
+        """(rows per block, wavefronts) of the step kernel."""
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().bn_get_launch(self._ctx, ctypes.byref(r), ctypes.byref(w)), "bn_get_launch")
+        return r.value, w.value
 
     def close(self):
         if getattr(self, "_ctx", None):

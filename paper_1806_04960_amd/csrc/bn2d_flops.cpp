@@ -62,8 +62,17 @@ Consts make_consts(int nx, int ny, double x0, double x1, double y0, double y1, d
     K.e_up1 = std::exp(-K.a * K.dy); K.e_dn1 = std::exp(K.a * K.dy);
     K.e_uph = std::exp(-K.a * 0.5 * K.dy); K.e_dnh = std::exp(K.a * 0.5 * K.dy);
     K.so_thr = 10.0 * ag;
+    K.inv_dx = 1.0 / K.dx; K.inv_dy = 1.0 / K.dy; K.inv2dx = 1.0 / (2.0 * K.dx); K.inv2dy = 1.0 / (2.0 * K.dy);
+    K.inv_rho0 = 1.0 / rho0;
     return K;
 }
+
+struct ArrayStencil {
+    const real_t (*wq)[3][4];
+    const int (*wf)[3];
+    real_t q(int dj, int di, int k) const { return wq[dj][di][k]; }
+    int f(int dj, int di) const { return wf[dj][di]; }
+};
 
 }  // namespace
 
@@ -77,15 +86,7 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
     auto fluid = [&](int i, int j) {
         return i >= 0 && i < nx && j >= 0 && j < ny && (!solid || solid[(size_t)j * nx + i] == 0);
     };
-    auto flags = [&](int i, int j) {
-        int f = 0;
-        if (i < 0) f |= F_OUTW;
-        if (i >= nx) f |= F_OUTE;
-        if (j < 0) f |= F_OUTS;
-        if (j >= ny) f |= F_OUTN;
-        if (fluid(i, j)) f |= F_FLUID;
-        return f;
-    };
+    auto flags = [&](int i, int j) { return cell_flags(i, j, nx, ny, bc, fluid(i, j)); };
     std::vector<Rec> rec(plane);
     unsigned long long c_rec = 0, c_x = 0, c_y = 0, c_upd = 0, c_red = 0, cells = 0;
 
@@ -103,7 +104,8 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
                                             ? Q[k * plane + (size_t)jj * nx + ii] : (k == 0 || k == 3 ? 1.0 : 0.0);
                 }
             g_ops = 0;
-            reconstruct(K, wq, wf, j, real_t(Y0[i]), real_t(dt), rec[(size_t)j * nx + i]);
+            ArrayStencil st{wq, wf};
+            reconstruct(K, st, j, real_t(Y0[i]), real_t(dt), rec[(size_t)j * nx + i]);
             c_rec += g_ops;
         }
 
@@ -162,8 +164,8 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
                 dps[k] = DpS[k * plane + c]; dmn[k] = DmN[k * plane + c];
             }
             g_ops = 0;
-            update_x_part(qn, dpw, dme, rec[c].fdiff, dtdx, P);
-            update_finish(P, dps, dmn, rec[c].gdiff, rec[c].vol2, rec[c].vol3, dtv, dtdy, q);
+            update_partial(qn, dpw, dme, rec[c].fdiff, rec[c].gdiff, rec[c].vol2, rec[c].vol3, dtv, dtdx, dtdy, P);
+            update_finish(P, dps, dmn, dtdy, q);
             c_upd += g_ops;
             g_ops = 0;
             (void)detector_term(K, q);

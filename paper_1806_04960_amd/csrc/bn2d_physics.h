@@ -30,18 +30,46 @@ struct Consts {
     double e_up1, e_dn1;   // exp(-a dy), exp(+a dy): density ratio one row up / down
     double e_uph, e_dnh;   // exp(-a dy/2), exp(+a dy/2): ratio to the upper / lower edge
     double so_thr;         // 10 alpha_gas: second-order threshold (Sec. 3.4)
+    double inv_dx, inv_dy, inv2dx, inv2dy, inv_rho0;
 };
 
-enum : int { F_FLUID = 1, F_OUTW = 2, F_OUTE = 4, F_OUTS = 8, F_OUTN = 16 };
+// Cell flags: fluid, outside the grid on a side, and (F_TX, F_TY) outside across a transmissive
+// side in x or y.  Solid cells and cells outside across a reflective wall are mirrored.
+enum : int { F_FLUID = 1, F_OUTW = 2, F_OUTE = 4, F_OUTS = 8, F_OUTN = 16, F_TX = 32, F_TY = 64 };
+
+// Flags of cell (i, j) of an nx x ny grid with boundary types bc (W, E, S, N; 1 transmissive).
+BN_DEV int cell_flags(int i, int j, int nx, int ny, const int bc[4], bool fluid)
+{
+    int f = fluid ? F_FLUID : 0;
+    if (i < 0) f |= F_OUTW | (bc[0] == 1 ? F_TX : 0);
+    if (i >= nx) f |= F_OUTE | (bc[1] == 1 ? F_TX : 0);
+    if (j < 0) f |= F_OUTS | (bc[2] == 1 ? F_TY : 0);
+    if (j >= ny) f |= F_OUTN | (bc[3] == 1 ? F_TY : 0);
+    return f;
+}
 
 BN_DEV real_t sgn(real_t x) { return (real_t)((x > 0.0) - (x < 0.0)); }
+
+// 1/x: hardware reciprocal refined by two Newton steps (within an ulp of the quotient).
+#ifdef BN2D_HOST_COUNT
+BN_DEV real_t rcp(real_t x) { return 1.0 / x; }
+#else
+BN_DEV double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+#endif
 
 // Physical flux f (x) of Sec. 2.1 with alpha p = alpha k0 (rho/rho0 - 1) = k0 (alpha rho / rho0 - alpha).
 BN_DEV void flux_f(const Consts &K, const real_t q[4], real_t inv_q0, real_t f[4])
 {
     const real_t u = q[1] * inv_q0, v = q[2] * inv_q0;
     f[0] = q[1];
-    f[1] = q[1] * u + K.k0 * (q[0] / K.rho0 - q[3]);
+    f[1] = q[1] * u + K.k0 * (q[0] * K.inv_rho0 - q[3]);
     f[2] = q[1] * v;
     f[3] = 0.0;
 }
@@ -100,14 +128,14 @@ BN_DEV void edge_x(const Consts &K, const real_t qm[4], const real_t qp[4], real
     real_t ubar = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) d[k] = qp[k] - qm[k];
-    flux_f(K, qm, 1.0 / qm[0], fm);
-    flux_f(K, qp, 1.0 / qp[0], fp);
+    flux_f(K, qm, rcp(qm[0]), fm);
+    flux_f(K, qp, rcp(qp[0]), fp);
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
         real_t phi[4], t[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) phi[k] = qm[k] + s_gl[n] * d[k];
-        const real_t inv = 1.0 / phi[0];
+        const real_t inv = rcp(phi[0]);
         const real_t u = phi[1] * inv, v = phi[2] * inv;
         abs_a1(K, u, v, d, t);
 #pragma unroll
@@ -126,7 +154,7 @@ BN_DEV void edge_x(const Consts &K, const real_t qm[4], const real_t qp[4], real
 // alpha p - alpha^E p^E = k0 ((alpha rho - (alpha rho)^E)/rho0 - (alpha - alpha^E))  (gamma = 1).
 BN_DEV real_t press_fluct(const Consts &K, const real_t q[4], real_t e1, real_t aE)
 {
-    return K.k0 * ((q[0] - e1) / K.rho0 - (q[3] - aE));
+    return K.k0 * ((q[0] - e1) * K.inv_rho0 - (q[3] - aE));
 }
 
 // Well-balanced b_3 on one sub-interval (Sec. 3.3): fluctuation pressure jump plus the gravity
@@ -134,15 +162,16 @@ BN_DEV real_t press_fluct(const Consts &K, const real_t q[4], real_t e1, real_t 
 BN_DEV real_t b3(const Consts &K, const real_t qa[4], real_t e1a, real_t aEa, real_t Pa,
                                      real_t ya, const real_t qb[4], real_t e1b, real_t aEb, real_t Pb, real_t yb)
 {
-    real_t r = Pb - Pa;
-    if (yb != ya) {
-        const real_t abar = 0.5 * (qa[3] + qb[3]);
-        const real_t rbar = 0.5 * (qa[0] / qa[3] + qb[0] / qb[3]);
-        const real_t aEbar = 0.5 * (aEa + aEb);
-        const real_t rEbar = 0.5 * (e1a / aEa + e1b / aEb);
-        r += (abar * rbar - aEbar * rEbar) * K.g * (yb - ya);
-    }
-    return r;
+    // (the gravity part vanishes exactly when ya == yb; the kernel computes it anyway, without a
+    // branch, while the operation count skips it as the scheme does)
+#ifdef BN2D_HOST_COUNT
+    if (yb == ya) return Pb - Pa;
+#endif
+    const real_t abar = 0.5 * (qa[3] + qb[3]);
+    const real_t rbar = 0.5 * (qa[0] * rcp(qa[3]) + qb[0] * rcp(qb[3]));
+    const real_t aEbar = 0.5 * (aEa + aEb);
+    const real_t rEbar = 0.5 * (e1a * rcp(aEa) + e1b * rcp(aEb));
+    return (Pb - Pa) + (abar * rbar - aEbar * rEbar) * K.g * (yb - ya);
 }
 
 // y-edge: well-balanced Osher-Romberg (Sec. 3.3, Romberg l = 3 of Sec. 3.1):
@@ -162,8 +191,8 @@ BN_DEV void edge_y(const Consts &K, const real_t qm[4], real_t e1m, real_t aEm, 
         q34[k] = qm[k] + 0.75 * d[k];
     }
     const real_t e1h = e1m + 0.5 * (e1p - e1m), aEh = aEm + 0.5 * (aEp - aEm), yh = ym + 0.5 * (yp - ym);
-    const real_t im = 1.0 / qm[0], ip = 1.0 / qp[0], i12 = 1.0 / q12[0];
-    const real_t i14 = 1.0 / q14[0], i34 = 1.0 / q34[0];
+    const real_t im = rcp(qm[0]), ip = rcp(qp[0]), i12 = rcp(q12[0]);
+    const real_t i14 = rcp(q14[0]), i34 = rcp(q34[0]);
     real_t gm[4], gh[4], gp[4];
     flux_g(qm, im, gm);
     flux_g(q12, i12, gh);
@@ -212,9 +241,21 @@ struct Rec {
 // gradients component by component, d_t Q = -(A1 d_x Q + A2 d_y Q) with grad Q = grad Q^E +
 // Psi grad Q^f.  Second order only if the centre and every fluid stencil cell hold liquid
 // (alpha > 10 alpha_gas); otherwise the first-order states of Sec. 3.2/3.3.
-BN_DEV void reconstruct(const Consts &K, const real_t (&wq)[3][3][4], const int (&wf)[3][3],
-                                            int j, real_t y0c, real_t dt, Rec &r)
+// The stencil is read through S: S.q(dj, di, k) is component k of the cell at row offset dj - 1 and
+// column offset di - 1, S.f(dj, di) its F_* flags.
+template <class S>
+BN_DEV void reconstruct(const Consts &K, const S &st, int j, real_t y0c, real_t dt, Rec &r)
 {
+    real_t wq[3][3][4];
+    int wf[3][3];
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+        for (int di = 0; di < 3; ++di) {
+            wf[dj][di] = st.f(dj, di);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wq[dj][di][k] = st.q(dj, di, k);
+        }
     const real_t *Qc = wq[1][1];
     const real_t yc = K.ylo + (j + 0.5) * K.dy;
     const bool liquid = yc < y0c;
@@ -244,35 +285,32 @@ BN_DEV void reconstruct(const Consts &K, const real_t (&wq)[3][3][4], const int 
     const real_t e1row[3] = {aE * (liquid ? rE0 * K.e_dn1 : K.rho0), e1c, aE * (liquid ? rE0 * K.e_up1 : K.rho0)};
     const real_t fc[4] = {Qc[0] - e1c, Qc[1], Qc[2], Qc[3] - aE};
 
+    // 3x3 fluctuations of all four components (neighbours with respect to this cell's profile;
+    // solid/outside neighbours mirror the centre across each reflective wall), then per component
+    // central gradients and the Barth-Jespersen limiter over the four edge midpoints, whose two
+    // x (y) midpoints carry +-d so that their ratios are (max - c)/|d| and (c - min)/|d|.
     real_t phi[3][3][4];
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
         for (int di = 0; di < 3; ++di) {
+            // (selects rather than branches: both forms are a few operations)
             const int f = wf[dj][di];
-            if (f & F_FLUID) {
-                phi[dj][di][0] = wq[dj][di][0] - e1row[dj];
-                phi[dj][di][1] = wq[dj][di][1];
-                phi[dj][di][2] = wq[dj][di][2];
-                phi[dj][di][3] = wq[dj][di][3] - aE;
-            } else {
-                // mirror of the centre across each separating reflective wall
-                const bool outx = f & (F_OUTW | F_OUTE), outy = f & (F_OUTS | F_OUTN);
-                const bool inside = !outx && !outy;
-                const bool fx = (di != 1) && (inside || (outx && K.bc[(f & F_OUTW) ? 0 : 1] == 0));
-                const bool fy = (dj != 1) && (inside || (outy && K.bc[(f & F_OUTS) ? 2 : 3] == 0));
-                phi[dj][di][0] = fc[0];
-                phi[dj][di][1] = fx ? -fc[1] : fc[1];
-                phi[dj][di][2] = fy ? -fc[2] : fc[2];
-                phi[dj][di][3] = fc[3];
-            }
+            const bool fluid = f & F_FLUID;
+            const bool outx = f & (F_OUTW | F_OUTE), outy = f & (F_OUTS | F_OUTN);
+            const bool inside = !outx && !outy;
+            const bool fx = (di != 1) && (inside || (outx && !(f & F_TX)));
+            const bool fy = (dj != 1) && (inside || (outy && !(f & F_TY)));
+            phi[dj][di][0] = fluid ? wq[dj][di][0] - e1row[dj] : fc[0];
+            phi[dj][di][1] = fluid ? wq[dj][di][1] : (fx ? -fc[1] : fc[1]);
+            phi[dj][di][2] = fluid ? wq[dj][di][2] : (fy ? -fc[2] : fc[2]);
+            phi[dj][di][3] = fluid ? wq[dj][di][3] - aE : fc[3];
         }
-
     real_t gx[4], gy[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const real_t gxr = (phi[1][2][k] - phi[1][0][k]) / (2.0 * K.dx);
-        const real_t gyr = (phi[2][1][k] - phi[0][1][k]) / (2.0 * K.dy);
+        const real_t gxr = (phi[1][2][k] - phi[1][0][k]) * K.inv2dx;
+        const real_t gyr = (phi[2][1][k] - phi[0][1][k]) * K.inv2dy;
         real_t mx = phi[1][1][k], mn = phi[1][1][k];
 #pragma unroll
         for (int dj = 0; dj < 3; ++dj)
@@ -281,19 +319,18 @@ BN_DEV void reconstruct(const Consts &K, const real_t (&wq)[3][3][4], const int 
                 mx = fmax(mx, phi[dj][di][k]);
                 mn = fmin(mn, phi[dj][di][k]);
             }
-        // Barth-Jespersen over the four edge midpoints: the two x (y) midpoints carry +-d, so
-        // their ratios are (max - c)/|d| and (c - min)/|d|.
         const real_t lim = fmin(mx - fc[k], fc[k] - mn);
         const real_t hx = fabs(gxr * (0.5 * K.dx)), hy = fabs(gyr * (0.5 * K.dy));
-        const real_t px = hx > 0.0 ? fmin(1.0, lim / hx) : 1.0;
-        const real_t py = hy > 0.0 ? fmin(1.0, lim / hy) : 1.0;
+        const real_t rx = fmin(1.0, lim * rcp(hx)), ry = fmin(1.0, lim * rcp(hy));  // discarded if h = 0
+        const real_t px = hx > 0.0 ? rx : 1.0;
+        const real_t py = hy > 0.0 ? ry : 1.0;
         const real_t psi = fmin(px, py);
         gx[k] = psi * gxr;
         gy[k] = psi * gyr;
     }
 
     // Hancock predictor with A1, A2 at the cell average (Sec. 3 matrices; rho c^2 - p = k0).
-    const real_t inv0 = 1.0 / Qc[0];
+    const real_t inv0 = rcp(Qc[0]);
     const real_t u = Qc[1] * inv0, v = Qc[2] * inv0;
     const real_t qy0 = gy[0] + aE * (liquid ? -K.a * rE0 : 0.0);
     real_t hdt[4];
@@ -332,41 +369,40 @@ BN_DEV void reconstruct(const Consts &K, const real_t (&wq)[3][3][4], const int 
     // Cell terms: the flux differences of the cell's own linear reconstruction and the midpoint
     // rule for the cell integral of B(q) grad q at (x_c, t^{n+1/2}) (Sec. 3.4).
     real_t fE[4], fW[4], gN[4], gS[4];
-    flux_f(K, r.qE, 1.0 / r.qE[0], fE);
-    flux_f(K, r.qW, 1.0 / r.qW[0], fW);
-    flux_g(r.qN, 1.0 / r.qN[0], gN);
-    flux_g(r.qS, 1.0 / r.qS[0], gS);
+    flux_f(K, r.qE, rcp(r.qE[0]), fE);
+    flux_f(K, r.qW, rcp(r.qW[0]), fW);
+    flux_g(r.qN, rcp(r.qN[0]), gN);
+    flux_g(r.qS, rcp(r.qS[0]), gS);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         r.fdiff[k] = fE[k] - fW[k];
         r.gdiff[k] = gN[k] - gS[k];
     }
     const real_t qc0 = Qc[0] + hdt[0];
-    const real_t ic = 1.0 / qc0;
+    const real_t ic = rcp(qc0);
     const real_t uc = (Qc[1] + hdt[1]) * ic, vc = (Qc[2] + hdt[2]) * ic;
-    r.vol2 = K.k0 * (gy[0] / K.rho0 - gy[3]) + (qc0 - e1c) * K.g;
+    r.vol2 = K.k0 * (gy[0] * K.inv_rho0 - gy[3]) + (qc0 - e1c) * K.g;
     r.vol3 = uc * gx[3] + vc * gy[3];
 }
 
 
 // Cell update (Sec. 3, eq. Scheme, with the cell's own flux difference [full system matrix]):
 //   Q^{n+1} = Q^n - dt/dx (D+_W + D-_E + f(q_E) - f(q_W)) - dt/dy (D+_S + D-_N + g(q_N) - g(q_S)) - dt B(q) grad q
-// split into the part known once the row's x-edges are solved and the part that needs the y-edge
-// above the row.
-BN_DEV void update_x_part(const real_t Qn[4], const real_t DpW[4], const real_t DmE[4], const real_t fdiff[4],
-                          real_t dtdx, real_t P[4])
+// split into everything known once the row's x-edges are solved, X, and the y-edge terms.
+BN_DEV void update_partial(const real_t Qn[4], const real_t DpW[4], const real_t DmE[4], const real_t fdiff[4],
+                           const real_t gdiff[4], real_t vol2, real_t vol3, real_t dt, real_t dtdx, real_t dtdy,
+                           real_t X[4])
 {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) P[k] = Qn[k] - dtdx * ((DpW[k] + DmE[k]) + fdiff[k]);
+    for (int k = 0; k < 4; ++k) X[k] = Qn[k] - dtdx * ((DpW[k] + DmE[k]) + fdiff[k]) - dtdy * gdiff[k];
+    X[2] = X[2] - dt * vol2;
+    X[3] = X[3] - dt * vol3;
 }
 
-BN_DEV void update_finish(const real_t P[4], const real_t DpS[4], const real_t DmN[4], const real_t gdiff[4],
-                          real_t vol2, real_t vol3, real_t dt, real_t dtdy, real_t q[4])
+BN_DEV void update_finish(const real_t X[4], const real_t DpS[4], const real_t DmN[4], real_t dtdy, real_t q[4])
 {
-    q[0] = P[0] - dtdy * ((DpS[0] + DmN[0]) + gdiff[0]);
-    q[1] = P[1] - dtdy * ((DpS[1] + DmN[1]) + gdiff[1]);
-    q[2] = P[2] - dtdy * ((DpS[2] + DmN[2]) + gdiff[2]) - dt * vol2;
-    q[3] = P[3] - dtdy * ((DpS[3] + DmN[3]) + gdiff[3]) - dt * vol3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = X[k] - dtdy * (DpS[k] + DmN[k]);
 }
 
 // Free-surface detector term of a fluid cell (Sec. 3.5) and its CFL rate (|u|+c)/dx + (|v|+c)/dy.
@@ -374,8 +410,8 @@ BN_DEV real_t detector_term(const Consts &K, const real_t q[4]) { return (q[3] -
 
 BN_DEV real_t cfl_rate(const Consts &K, const real_t q[4])
 {
-    const real_t iq = 1.0 / q[0];
-    return (fabs(q[1] * iq) + K.c) / K.dx + (fabs(q[2] * iq) + K.c) / K.dy;
+    const real_t iq = rcp(q[0]);
+    return (fabs(q[1] * iq) + K.c) * K.inv_dx + (fabs(q[2] * iq) + K.c) * K.inv_dy;
 }
 
 }  // namespace bn

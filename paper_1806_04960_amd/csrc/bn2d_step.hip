@@ -1,19 +1,36 @@
 // Fused explicit step of the well-balanced Osher-Romberg scheme (Gaburro, Castro, Dumbser,
 // arXiv:1806.04960, Sec. 3) for gfx950, FP64 on the vector ALUs.
 //
-// Work decomposition.  One wavefront (64 lanes) owns a strip of 64 columns, lane L holding
-// column i0 - 2 + L, and marches upwards through H rows.  Per row it loads one row of the
-// state (coalesced, one 8-byte value per lane and plane), keeps the 3 x 3 stencil window of the
-// state in registers (neighbour columns through cross-lane shuffles), reconstructs the row below
-// the newest one, computes every x-edge of that row and the y-edge below it exactly once, and
-// finishes the row below that: the edge fluctuations a row needs are all in its own lane or in
-// the adjacent lane, so nothing but the state crosses HBM.  Lanes 2..61 produce output; lanes
-// 0, 1, 62, 63 are the column halo (lanes 1 and 62 reconstruct, 0 and 63 only load).
+// Marching.  A wavefront (64 lanes) works on a strip of 64 columns, lane L holding column
+// 60 s - 2 + L of strip s, and marches upwards through a range of rows.  Per row it loads one row
+// of the state (coalesced, 8 bytes per lane and plane, prefetched one row ahead), keeps the last
+// three rows in an LDS ring, reconstructs the row below the newest one, solves every x-edge of that
+// row and the y-edge below it exactly once, and finishes the row below that: the edge
+// fluctuations a cell needs come from its own lane or the adjacent lane, so nothing but the state
+// crosses HBM.  Lanes 2..61 produce output; lanes 0, 1, 62, 63 are the column halo (1 and 62
+// reconstruct).  A range that starts at row j0 first reconstructs row j0 - 1 (halo below) and
+// ends by reconstructing the row above its last one (halo above).
 //
-// Besides Q^{n+1} the kernel writes, per column and row block, the partial sum of
-// (alpha - alpha_g)/(alpha_l - alpha_g) over the fluid cells it updated (the free-surface
-// detector of Sec. 3.5 for the next step, summed upward), and folds the CFL rate of every
-// updated cell into one 64-bit atomic max.
+// Scheduling.  The launch is persistent: one wavefront per SIMD.  Every marched range records
+// its duration per row; the next step cuts the strips into one range per wavefront of equal
+// recorded cost (second-order liquid rows cost about 1.5x first-order gas rows, rows across the
+// free surface more), so that all wavefronts finish together as long as the flow changes little
+// from one step to the next.  A strip head below the first cut is left unowned.  A wavefront
+// claims B rows of its range at a time with an atomic add on the range's descriptor, issued a
+// row ahead so that the claim does not stall the march, and keeps marching through consecutive
+// claims without repeating the halo.  When its range is exhausted it takes an unowned range or
+// splits a range still being marched, taking its upper half (one compare-and-swap on the
+// descriptor), which absorbs what the recorded costs did not predict.  The partition depends on
+// timing, the results do not: every cell is computed by the same arithmetic whoever marches it.
+// No wavefront ever waits for another.
+//
+// Reductions.  The free-surface integral of the next step (Sec. 3.5) is accumulated per column in
+// 64-bit fixed point with atomic adds, which makes it independent of the order in which rows are
+// processed and so of the schedule; the CFL rate is folded into a 64-bit atomic max.  The last
+// wavefront to finish turns the maximum rate into the next dt.  The fixed-point integrals are
+// triple-buffered (read, accumulate, clear for the next step), as are the per-strip cost totals;
+// dt, the CFL maximum, the per-row costs and the range lists are double-buffered, each step
+// clearing the next step's list.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,174 +38,306 @@
 
 namespace bn {
 
+// Everything the step needs besides the hot pointers, for one combination of buffer rotations.
+// It lives in device memory and is read through the scalar cache at the few places it is used.
+struct Control {
+    const int *jb;                  // first fluid row of each column
+    const long long *S_in;          // fixed-point free-surface integral of Q (read)
+    long long *S_out;               // ... of Qn (accumulated)
+    long long *S_clear;             // third buffer, zeroed for the next step
+    double fix_scale, fix_inv;      // fixed-point scale 2^f and 2^-f
+    unsigned long long *desc;       // range descriptors of this step
+    int *nranges;                   // published descriptors of this step
+    unsigned long long *desc_next;  // range descriptors of the next step (initialised here)
+    int *nranges_next;
+    const float *cost_in;           // [nstrips][ny] recorded cost per row (previous step)
+    float *cost_out;                // ... recorded by this step
+    const double *Ts_in;            // [nstrips] recorded cost per strip (previous step)
+    double *Ts_out;                 // ... accumulated by this step
+    double *Ts_clear;               // third buffer, zeroed for the next step
+    const double *dt_dev;           // dt of this step computed by the previous one (run mode)
+    double *dt_out;                 // CFL dt of Qn
+    double *t;                      // elapsed time
+    unsigned long long *lam_acc;    // CFL max of Qn (accumulated here)
+    unsigned long long *lam_clear;  // the other slot, zeroed for the next step
+    int *done;                      // finished wavefronts
+    int *flag;                      // 1: non-physical state, 2: no CFL rate, 4: scheduler error
+    int B;                          // rows per claim
+    int ny;                         // rows per strip
+    int nstrips;                    // column strips
+    int R0;                         // initial descriptors: one per wavefront, one head per strip
+    int max_slots;                  // descriptor capacity (initial descriptors and splits)
+    int P;                          // wavefronts of the launch
+};
+
+struct StepArgs {
+    const double *Q;                // state at t^n
+    double *Qn;                     // state at t^{n+1}
+    const uint8_t *solid;           // nx*ny mask or null
+    unsigned long long kaddr;       // device address of the Consts
+    unsigned long long caddr;       // device address of the Control
+    double dt_arg;                  // dt of this step (explicit mode)
+    int use_dt_dev;                 // 1: take dt from Control::dt_dev
+    int nx, ny, B;
+};
+
+// The physical constants and the Control are read through an address the compiler must treat as
+// new at every use site (an empty asm that "modifies" it), so their scalar loads are repeated
+// where needed instead of being held in scalar registers across the march.
+typedef const __attribute__((address_space(4))) Consts *ConstsPtr;
+typedef const __attribute__((address_space(4))) Control *ControlPtr;
+__device__ __forceinline__ const Consts &consts_at(unsigned long long addr)
+{
+    asm volatile("" : "+s"(addr));
+    return *(const Consts *)(ConstsPtr)addr;
+}
+__device__ __forceinline__ const Control &control_at(unsigned long long addr)
+{
+    asm volatile("" : "+s"(addr));
+    return *(const Control *)(ControlPtr)addr;
+}
+
+// Range descriptor: one 64-bit word, [63] owned, [62:48] strip, [47:24] end row (exclusive),
+// [23:0] next unclaimed row.  The owner claims with an atomic add of B; a thief lowers the end.
+constexpr unsigned long long kOwned = 1ull << 63;
+__host__ __device__ inline int d_cur(unsigned long long d) { return (int)(d & 0xFFFFFFull); }
+__host__ __device__ inline int d_end(unsigned long long d) { return (int)((d >> 24) & 0xFFFFFFull); }
+__host__ __device__ inline int d_strip(unsigned long long d) { return (int)((d >> 48) & 0x7FFFull); }
+__host__ __device__ inline unsigned long long d_make(bool owned, int strip, int end, int cur)
+{
+    return (owned ? kOwned : 0ull) | ((unsigned long long)strip << 48) | ((unsigned long long)end << 24) |
+           (unsigned long long)cur;
+}
+
+__device__ __forceinline__ unsigned long long load_word(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ double shfl_from_left(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double shfl_from_right(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ int shfl_from_left(int v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ int shfl_from_right(int v) { return __shfl_down(v, 1, 64); }
 
-__global__ __launch_bounds__(64) void step_kernel(const double *__restrict__ Q, double *__restrict__ Qn,
-                                                   const uint8_t *__restrict__ solid, const double *__restrict__ Y0,
-                                                   const double *__restrict__ dt_dev, double dt_arg,
-                                                   double *__restrict__ partial, unsigned long long *lam_slot,
-                                                   int *flag, Consts K, int H)
+__device__ __forceinline__ double wave_incl_scan(double v)
 {
     const int lane = threadIdx.x;
-    const int i = (int)blockIdx.x * 60 - 2 + lane;
-    const int j0 = (int)blockIdx.y * H;
-    const bool colin = i >= 0 && i < K.nx;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// For each target t[k]: the index i of v[0..n) with v[0] + ... + v[i-1] <= t[k] < v[0] + ... + v[i]
+// (n if there is none) and t[k] minus the lower bound.  Read in chunks of 64.
+template <int NT, class T>
+__device__ void locate(const T *v, int n, const double (&t)[NT], int (&idx)[NT], double (&off)[NT])
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        idx[k] = n;
+        off[k] = 0.0;
+    }
+    double base = 0.0;
+    for (int c = 0; c < n; c += 64) {
+        const int i = c + lane;
+        const double val = i < n ? (double)v[i] : 0.0;
+        const double incl = base + wave_incl_scan(val), excl = incl - val;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (idx[k] != n) continue;
+            const unsigned long long m = __ballot(i < n && excl <= t[k] && t[k] < incl);
+            if (m) {
+                const int l = __ffsll((long long)m) - 1;
+                idx[k] = c + l;
+                off[k] = t[k] - __shfl(excl, l, 64);
+            }
+        }
+        base = __shfl(incl, 63, 64);
+    }
+}
+
+// Stencil accessor over the LDS ring: rows s[0..2] (below, centre, above), lane offsets -1..1.
+struct LdsStencil {
+    const double (*sq)[4][64];
+    const int (*sf)[64];
+    int s[3];
+    int lane;
+    __device__ __forceinline__ double q(int dj, int di, int k) const { return sq[s[dj]][k][lane + di - 1]; }
+    __device__ __forceinline__ int f(int dj, int di) const { return sf[s[dj]][lane + di - 1]; }
+};
+
+// March strip `strip` upwards from row j0, rows [j0, E) already claimed, claiming further rows
+// through descriptor `slot` (none if slot < 0) until a claim fails.
+__device__ void march(const StepArgs &a, unsigned long long ka, unsigned long long ca, double (*sq)[4][64],
+                      int (*sf)[64], int strip, int j0, int E, int slot, double dt, double dtdx, double dtdy,
+                      double &lam, int &bad)
+{
+    const int lane = threadIdx.x;
+    const int i = strip * 60 - 2 + lane;
+    const bool colin = i >= 0 && i < a.nx;
     const bool out_lane = colin && lane >= 2 && lane < 62;
     const bool rec_lane = lane >= 1 && lane <= 62;
-    const size_t plane = (size_t)K.nx * K.ny;
-    const double dt = dt_dev ? *dt_dev : dt_arg;
-    const double dtdx = dt / K.dx, dtdy = dt / K.dy;
-    const double y0c = colin ? Y0[i] : 0.0;
+    const size_t plane = (size_t)a.nx * a.ny;
+    double y0c = 0.0;
+    if (colin) {
+        const Consts &K = consts_at(ka);
+        const Control &C = control_at(ca);
+        y0c = (K.ylo + C.jb[i] * K.dy) + K.dy * ((double)C.S_in[i] * C.fix_inv);
+    }
+    unsigned long long *desc = slot >= 0 ? control_at(ca).desc + slot : nullptr;
+    bool outstanding = false, last = slot < 0;
+    const long long t_begin = clock64();
+    unsigned long long claim = 0;
 
-    double wq[3][3][4];
-    int wf[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            wf[a][b] = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) wq[a][b][k] = 1.0;
-        }
-
-    // pending row (the one below the row being reconstructed)
-    double pP[4] = {0, 0, 0, 0}, pDpS[4] = {0, 0, 0, 0}, pG[4] = {0, 0, 0, 0}, pV2 = 0.0, pV3 = 0.0;
+    // pending row (below the row being reconstructed): its update without the y-edge terms, the
+    // D+ of its south edge, and its north edge state
+    double pX[4] = {0, 0, 0, 0}, pDpS[4] = {0, 0, 0, 0};
     double nQ[4] = {1, 0, 0, 1}, nE1 = 1.0, nAE = 1.0, nY = 0.0;
     int nF = 0;
-    double colsum = 0.0, lam = 0.0;
-    int bad = 0;
+    long long colfix = 0;
 
-    for (int r = j0 - 2; r <= j0 + H + 1; ++r) {
-        // ---- shift the window and load row r --------------------------------------------
+    // row prefetch
+    double lq[4];
+    int lf;
+    // (the address is clamped into the grid and the value replaced outside it, so that the load
+    // needs no branch)
+    auto load_row = [&](int r) {
+        const bool in = colin && r >= 0 && r < a.ny;
+        const size_t cidx = (size_t)min(max(r, 0), a.ny - 1) * a.nx + min(max(i, 0), a.nx - 1);
+        bool fluid = in;
+        if (a.solid) fluid = fluid && a.solid[cidx] == 0;
+        const double dflt[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                wf[a][b] = wf[a + 1][b];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) wq[a][b][k] = wq[a + 1][b][k];
-            }
-        {
-            const bool rowin = r >= 0 && r < K.ny;
-            int f = 0;
-            double q[4] = {1.0, 0.0, 0.0, 1.0};
-            if (!colin) f |= (i < 0) ? F_OUTW : F_OUTE;
-            if (!rowin) f |= (r < 0) ? F_OUTS : F_OUTN;
-            if (colin && rowin) {
-                const size_t cidx = (size_t)r * K.nx + i;
-                if (!solid || solid[cidx] == 0) f |= F_FLUID;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) q[k] = Q[k * plane + cidx];
-            }
-            wf[2][1] = f;
-            wf[2][0] = shfl_from_left(f);
-            wf[2][2] = shfl_from_right(f);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                wq[2][1][k] = q[k];
-                wq[2][0][k] = shfl_from_left(q[k]);
-                wq[2][2][k] = shfl_from_right(q[k]);
-            }
+        for (int k = 0; k < 4; ++k) {
+            const double v = a.Q[k * plane + cidx];
+            lq[k] = in ? v : dflt[k];
         }
+        lf = cell_flags(i, r, a.nx, a.ny, consts_at(ka).bc, fluid);
+    };
+    load_row(j0 - 2);
+
+    int s_hi = 2;  // ring slot that receives row r
+    for (int r = j0 - 2;; ++r) {
+        // the claim of the rows from E on is resolved when row E is about to be reconstructed,
+        // and the next claim goes out a row before it is needed
+        if (outstanding && r == E + 1) {
+            const unsigned long long c = __shfl(claim, 0, 64);
+            outstanding = false;
+            if (d_cur(c) < d_end(c)) E = min(E + a.B, d_end(c));  // d_cur(c) == E: only the owner advances it
+            else last = true;
+        }
+        if (!last && !outstanding && r >= E - 1) {
+            if (lane == 0) claim = atomicAdd(desc, (unsigned long long)a.B);
+            outstanding = true;
+        }
+        const bool final_row = last && r == E + 1;
+
+        s_hi = (s_hi == 2) ? 0 : s_hi + 1;
+        const int s_mid = (s_hi == 0) ? 2 : s_hi - 1;
+        const int s_lo = (s_mid == 0) ? 2 : s_mid - 1;
+        __syncthreads();  // the slot about to be overwritten is no longer read
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sq[s_hi][k][lane] = lq[k];
+        sf[s_hi][lane] = lf;
+        if (!final_row) load_row(r + 1);
+        __syncthreads();
         if (r < j0) continue;
 
         // ---- reconstruct row jr = r - 1 ----------------------------------------------------
         const int jr = r - 1;
-        const bool fl = rec_lane && (wf[1][1] & F_FLUID);
+        const int fc_mid = sf[s_mid][lane];
+        const bool fl = rec_lane && (fc_mid & F_FLUID);
         Rec rc;
         if (fl) {
-            reconstruct(K, wq, wf, jr, y0c, dt, rc);
+            const Consts &K = consts_at(ka);
+            LdsStencil st{sq, sf, {s_lo, s_mid, s_hi}, lane};
+            reconstruct(K, st, jr, y0c, dt, rc);
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                rc.qW[k] = wq[1][1][k]; rc.qE[k] = wq[1][1][k]; rc.qS[k] = wq[1][1][k]; rc.qN[k] = wq[1][1][k];
+                const double v = sq[s_mid][k][lane];
+                rc.qW[k] = v; rc.qE[k] = v; rc.qS[k] = v; rc.qN[k] = v;
                 rc.fdiff[k] = 0.0; rc.gdiff[k] = 0.0;
             }
             rc.e1S = 1.0; rc.e1N = 1.0; rc.aE = 1.0; rc.yS = 0.0; rc.yN = 0.0; rc.vol2 = 0.0; rc.vol3 = 0.0;
         }
-        const bool jr_inside_block = jr >= j0 && jr < j0 + H;
+        const bool jr_inside = jr >= j0 && jr < E;
 
-        // ---- x-edges of row jr: lane L solves the edge between columns L and L+1 ------------
-        double DpW[4] = {0, 0, 0, 0}, DmE[4] = {0, 0, 0, 0};
-        if (jr_inside_block) {
+        // ---- x-edges of row jr: lane L solves the edge between columns L and L+1, then every
+        // term of the update of row jr except those of its two y-edges.  Lanes whose edge or
+        // cell is not needed compute on benign copies and discard the result. -----------------
+        double X[4] = {0, 0, 0, 0};
+        if (jr_inside) {
+            const Consts &K = consts_at(ka);
             double qWr[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) qWr[k] = shfl_from_right(rc.qW[k]);
-            const int fR = shfl_from_right(wf[1][1]);
+            const int fR = shfl_from_right(fc_mid);
             const bool rf = (lane <= 61) && (fR & F_FLUID);
-            double Dm[4] = {0, 0, 0, 0}, Dp[4] = {0, 0, 0, 0};
-            if (fl || rf) {
-                double qm[4], qp[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    qm[k] = fl ? rc.qE[k] : qWr[k];
-                    qp[k] = rf ? qWr[k] : rc.qE[k];
-                }
-                // wall: mirror state with negated normal momentum, or a copy on a transmissive side
-                if (!fl && !((wf[1][1] & F_OUTW) && K.bc[0] == 1)) qm[1] = -qm[1];
-                if (!rf && !((fR & F_OUTE) && K.bc[1] == 1)) qp[1] = -qp[1];
-                edge_x(K, qm, qp, Dm, Dp);
-            }
+            double qm[4], qp[4], Dm[4], Dp[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                DmE[k] = Dm[k];
-                DpW[k] = shfl_from_left(Dp[k]);
+                qm[k] = fl ? rc.qE[k] : qWr[k];
+                qp[k] = rf ? qWr[k] : rc.qE[k];
             }
+            // wall: mirror state with negated normal momentum, or a copy on a transmissive side
+            if (!fl && !(fc_mid & F_TX)) qm[1] = -qm[1];
+            if (!rf && !(fR & F_TX)) qp[1] = -qp[1];
+            edge_x(K, qm, qp, Dm, Dp);
+            double DpW[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) DpW[k] = shfl_from_left(Dp[k]);
+            const double Qm[4] = {sq[s_mid][0][lane], sq[s_mid][1][lane], sq[s_mid][2][lane], sq[s_mid][3][lane]};
+            update_partial(Qm, DpW, Dm, rc.fdiff, rc.gdiff, rc.vol2, rc.vol3, dt, dtdx, dtdy, X);
         }
 
         // ---- y-edge between row jr-1 (pending north state) and row jr ----------------------
         double DyM[4] = {0, 0, 0, 0}, DyP[4] = {0, 0, 0, 0};
         if (r > j0) {
+            const Consts &K = consts_at(ka);
             const bool bf = rec_lane && (nF & F_FLUID);
-            if (bf || fl) {
-                double qm[4], qp[4], e1m, aEm, ym, e1p, aEp, yp;
+            double qm[4], qp[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    qm[k] = bf ? nQ[k] : rc.qS[k];
-                    qp[k] = fl ? rc.qS[k] : nQ[k];
-                }
-                e1m = bf ? nE1 : rc.e1S; aEm = bf ? nAE : rc.aE; ym = bf ? nY : rc.yS;
-                e1p = fl ? rc.e1S : nE1; aEp = fl ? rc.aE : nAE; yp = fl ? rc.yS : nY;
-                if (!bf && !((nF & F_OUTS) && K.bc[2] == 1)) qm[2] = -qm[2];
-                if (!fl && !((wf[1][1] & F_OUTN) && K.bc[3] == 1)) qp[2] = -qp[2];
-                edge_y(K, qm, e1m, aEm, ym, qp, e1p, aEp, yp, DyM, DyP);
+            for (int k = 0; k < 4; ++k) {
+                qm[k] = bf ? nQ[k] : rc.qS[k];
+                qp[k] = fl ? rc.qS[k] : nQ[k];
             }
+            const double e1m = bf ? nE1 : rc.e1S, aEm = bf ? nAE : rc.aE, ym = bf ? nY : rc.yS;
+            const double e1p = fl ? rc.e1S : nE1, aEp = fl ? rc.aE : nAE, yp = fl ? rc.yS : nY;
+            if (!bf && !(nF & F_TY)) qm[2] = -qm[2];
+            if (!fl && !(fc_mid & F_TY)) qp[2] = -qp[2];
+            edge_y(K, qm, e1m, aEm, ym, qp, e1p, aEp, yp, DyM, DyP);
         }
 
         // ---- finish row jr-1 ---------------------------------------------------------------
         const int jf = jr - 1;
-        if (r > j0 && jf >= j0 && jf < j0 + H && out_lane && jf < K.ny) {
-            const size_t cidx = (size_t)jf * K.nx + i;
-            const int ff = wf[0][1];
-            if (ff & F_FLUID) {
-                double qn[4];
-                update_finish(pP, pDpS, DyM, pG, pV2, pV3, dt, dtdy, qn);
+        if (jf >= j0 && jf < a.ny && out_lane) {
+            const Consts &K = consts_at(ka);
+            const Control &C = control_at(ca);
+            const size_t cidx = (size_t)jf * a.nx + i;
+            const bool fluid = sf[s_lo][lane] & F_FLUID;  // solid cells keep their values
+            double qn[4];
+            update_finish(pX, pDpS, DyM, dtdy, qn);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) Qn[k * plane + cidx] = qn[k];
-                colsum += detector_term(K, qn);
-                lam = fmax(lam, cfl_rate(K, qn));
-                if (!(qn[0] > 0.0) || !(qn[3] > 0.0) || !isfinite(qn[0]) || !isfinite(qn[1]) ||
-                    !isfinite(qn[2]) || !isfinite(qn[3]))
-                    bad = 1;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) Qn[k * plane + cidx] = wq[0][1][k];
-            }
+            for (int k = 0; k < 4; ++k) a.Qn[k * plane + cidx] = fluid ? qn[k] : sq[s_lo][k][lane];
+            const long long term = __double2ll_rn(detector_term(K, qn) * C.fix_scale);
+            const double rate = cfl_rate(K, qn);
+            colfix += fluid ? term : 0ll;
+            lam = fluid ? fmax(lam, rate) : lam;
+            const bool ok = qn[0] > 0.0 && qn[3] > 0.0 && isfinite(qn[0]) && isfinite(qn[1]) && isfinite(qn[2]) &&
+                            isfinite(qn[3]);
+            bad |= (fluid && !ok) ? 1 : 0;
         }
+        if (final_row) break;
 
         // ---- row jr becomes the pending row ------------------------------------------------
-        if (jr_inside_block && fl) {
-            update_x_part(wq[1][1], DpW, DmE, rc.fdiff, dtdx, pP);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                pDpS[k] = DyP[k];
-                pG[k] = rc.gdiff[k];
-            }
-            pV2 = rc.vol2;
-            pV3 = rc.vol3;
+        for (int k = 0; k < 4; ++k) {
+            pX[k] = X[k];
+            pDpS[k] = DyP[k];
         }
         if (fl) {
 #pragma unroll
@@ -197,44 +346,230 @@ __global__ __launch_bounds__(64) void step_kernel(const double *__restrict__ Q, 
             nAE = rc.aE;
             nY = rc.yN;
         }
-        nF = wf[1][1];
+        nF = fc_mid;
+    }
+    const Control &C = control_at(ca);
+    if (out_lane && colfix != 0) atomicAdd((unsigned long long *)&C.S_out[i], (unsigned long long)colfix);
+
+    // recorded cost of the rows marched here, for the next step's partition
+    const double spent = (double)(clock64() - t_begin);
+    const float per_row = (float)(spent / (E - j0));
+    for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[(size_t)strip * C.ny + rr] = per_row;
+    if (lane == 0) atomicAdd(&C.Ts_out[strip], spent);
+}
+
+// A split costs the thief a halo (two extra reconstructed rows and a row of loads), so only ranges
+// with at least this many unclaimed rows are split.
+constexpr int kMinSplit = 8;
+
+// Find work: a range nobody owns (taken whole) or a large range being marched with at least
+// kMinSplit unclaimed rows (upper half taken).  Returns false when there is none.  On success the
+// caller has claimed rows [*j0, *E) of strip *strip and owns descriptor *slot (-1: the rows up to
+// *E are all it gets, when the descriptor list is full).
+__device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E, int *slot)
+{
+    const int lane = threadIdx.x;
+    const Control &a = control_at(ca);
+    for (int attempt = 0; attempt < 4096; ++attempt) {
+        int n = __hip_atomic_load(a.nranges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        n = n < a.max_slots ? n : a.max_slots;
+        // key = score << 40 | hash << 32 | (2^31 - 1 - slot): larger is better
+        long long best = 0;
+        for (int base = 0; base < n; base += 64 * 8) {
+            unsigned long long wd[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int s = base + u * 64 + lane;
+                wd[u] = s < n ? load_word(a.desc + s) : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int s = base + u * 64 + lane;
+                const int rem = d_end(wd[u]) - d_cur(wd[u]);
+                // unowned ranges first, then by size class (floor log2 of the unclaimed rows);
+                // within a class a hash of (slot, thief) spreads the thieves over the victims
+                long long score = 0;
+                if (!(wd[u] & kOwned) && rem >= 1) score = 64 + (31 - __clz(rem));
+                else if ((wd[u] & kOwned) && rem >= kMinSplit) score = 31 - __clz(rem);
+                if (score > 0 && s < n) {
+                    const unsigned h = ((unsigned)s * 2654435761u) ^ ((unsigned)blockIdx.x * 40503u + attempt);
+                    const long long key = (score << 40) | ((long long)(h & 0xFFu) << 32) | (long long)(0x7FFFFFFF - s);
+                    best = key > best ? key : best;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const long long o = __shfl_xor(best, off, 64);
+            best = o > best ? o : best;
+        }
+        if (best == 0) return false;
+        const int s = 0x7FFFFFFF - (int)(best & 0xFFFFFFFFll);
+        int ok = 0, st = 0, r0 = 0, r1 = 0, sl = 0;
+        if (lane == 0) {
+            unsigned long long *p = a.desc + s;
+            const unsigned long long old = load_word(p);
+            const int cur = d_cur(old), end = d_end(old);
+            if (!(old & kOwned) && end - cur >= 1) {
+                if (atomicCAS(p, old, (old | kOwned) + (unsigned long long)B) == old) {
+                    ok = 1; st = d_strip(old); r0 = cur; r1 = min(cur + B, end); sl = s;
+                }
+            } else if ((old & kOwned) && end - cur >= kMinSplit) {
+                const int mid = cur + (end - cur) / 2;
+                const unsigned long long lowered = (old & ~(0xFFFFFFull << 24)) | ((unsigned long long)mid << 24);
+                if (atomicCAS(p, old, lowered) == old) {
+                    ok = 1; st = d_strip(old); r0 = mid;
+                    const int k = atomicAdd(a.nranges, 1);
+                    if (k < a.max_slots) {
+                        atomicExch(a.desc + k, d_make(true, st, end, min(mid + B, end)));
+                        r1 = min(mid + B, end); sl = k;
+                    } else {
+                        r1 = end; sl = -1;  // list full: march the whole upper half unpublished
+                    }
+                }
+            }
+        }
+        ok = __shfl(ok, 0, 64);
+        if (ok) {
+            *strip = __shfl(st, 0, 64);
+            *j0 = __shfl(r0, 0, 64);
+            *E = __shfl(r1, 0, 64);
+            *slot = __shfl(sl, 0, 64);
+            return true;
+        }
+    }
+    if (lane == 0) atomicOr(a.flag, 4);
+    return false;
+}
+
+__global__ __launch_bounds__(64) void step_kernel(StepArgs a)
+{
+    __shared__ double sq[3][4][64];
+    __shared__ int sf[3][64];
+
+    const int lane = threadIdx.x, w = blockIdx.x;
+    const unsigned long long ka = a.kaddr, ca = a.caddr;
+    double dt, dtdx, dtdy;
+    {
+        const Consts &K = consts_at(ka);
+        const Control &C = control_at(ca);
+        dt = a.use_dt_dev ? *C.dt_dev : a.dt_arg;
+        dtdx = dt * K.inv_dx;
+        dtdy = dt * K.inv_dy;
+
+        // the next step's range list and accumulators (this step does not touch them otherwise)
+        for (int s = w * 64 + lane; s < C.max_slots; s += C.P * 64) C.desc_next[s] = 0ull;
+        for (int c = w * 64 + lane; c < a.nx; c += C.P * 64) C.S_clear[c] = 0;
+        for (int c = w * 64 + lane; c < C.nstrips; c += C.P * 64) C.Ts_clear[c] = 0.0;
+        if (w == 0 && lane == 0) *C.nranges_next = C.R0;
     }
 
-    if (out_lane) partial[(size_t)blockIdx.y * K.nx + i] = colsum;
+    double lam = 0.0;
+    int bad = 0;
+
+    // ---- this wavefront's range: the cost interval [w, w+1) T/P of the recorded costs ---------
+    int strip = 0, j0 = 0, E = 0, slot = w;
+    bool have = false;
+    {
+        const Control &C = control_at(ca);
+        double total = 0.0;
+        for (int c = lane; c < C.nstrips; c += 64) total += C.Ts_in[c];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
+        const double step = total / C.P;
+        const double xs[3] = {w > 0 ? (w - 1) * step : -1.0, w * step, w + 1 < C.P ? (w + 1) * step : total};
+        int sidx[3];
+        double soff[3];
+        locate<3>(C.Ts_in, C.nstrips, xs, sidx, soff);
+        const int s_prev = w > 0 ? sidx[0] : -1, s_w = sidx[1], s_next = sidx[2];
+        if (s_w < C.nstrips) {
+            const double rt[2] = {soff[1], s_next == s_w ? soff[2] : 1e300};
+            int ridx[2];
+            double roff[2];
+            locate<2>(C.cost_in + (size_t)s_w * C.ny, C.ny, rt, ridx, roff);
+            const int lo = ridx[0], hi = s_next == s_w ? ridx[1] : C.ny;
+            // published with atomic stores: other wavefronts read and update them atomically
+            if (lane == 0) {
+                if (lo < hi) atomicExch(C.desc + w, d_make(true, s_w, hi, min(lo + a.B, hi)));
+                // the head of the first strip this wavefront cuts, and strips it spans whole, unowned
+                if (s_prev < s_w && lo > 0) atomicExch(C.desc + C.P + s_w, d_make(false, s_w, lo, 0));
+            }
+            for (int s = s_w + 1 + lane; s < s_next && s < C.nstrips; s += 64)
+                atomicExch(C.desc + C.P + s, d_make(false, s, C.ny, 0));
+            if (lo < hi) {
+                have = true;
+                strip = s_w;
+                j0 = lo;
+                E = min(lo + a.B, hi);
+            }
+        }
+        __threadfence();
+    }
+    if (!have) have = steal(ca, a.B, &strip, &j0, &E, &slot);
+    while (have) {
+        march(a, ka, ca, sq, sf, strip, j0, E, slot, dt, dtdx, dtdy, lam, bad);
+        have = steal(ca, a.B, &strip, &j0, &E, &slot);
+    }
+
+    // ---- CFL max and non-physical flag; the last wavefront computes the next dt ---------------
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         lam = fmax(lam, __shfl_xor(lam, off, 64));
         bad |= __shfl_xor(bad, off, 64);
     }
+    const Control &C = control_at(ca);
+    __threadfence();
+    int prior = 0;
     if (lane == 0) {
-        if (lam > 0.0) atomicMax(lam_slot, (unsigned long long)__double_as_longlong(lam));
-        if (bad) atomicOr(flag, 1);
+        if (lam > 0.0) atomicMax(C.lam_acc, (unsigned long long)__double_as_longlong(lam));
+        if (bad) atomicOr(C.flag, 1);
+        __threadfence();
+        prior = atomicAdd(C.done, 1);
+    }
+    prior = __shfl(prior, 0, 64);
+    if (prior != C.P - 1) return;
+
+    if (lane == 0) {
+        const Consts &K = consts_at(ka);
+        __threadfence();
+        const double lmax = __longlong_as_double(
+            (long long)__hip_atomic_load(C.lam_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        *C.t += dt;
+        if (lmax > 0.0 && isfinite(lmax)) {
+            *C.dt_out = K.cfl / lmax;
+        } else {
+            *C.dt_out = 0.0;
+            atomicOr(C.flag, 2);
+        }
+        *C.lam_clear = 0ull;
+        *C.done = 0;
     }
 }
 
-// Detector partial sums and CFL rate of a state (used after bn_set_state), same layout as the
-// step kernel's output: thread = column, blockIdx.y = row block.
+// Fixed-point free-surface integral and CFL rate of a state given through bn_set_state (thread =
+// column, blockIdx.y = block of H rows).  S must be zero on entry.
 __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q, const uint8_t *__restrict__ solid,
-                                                     double *__restrict__ partial, unsigned long long *lam_slot,
+                                                     long long *S, double fix_scale, unsigned long long *lam_slot,
                                                      int *flag, Consts K, int H)
 {
     const int i = (int)blockIdx.x * 64 + threadIdx.x;
     const size_t plane = (size_t)K.nx * K.ny;
-    double colsum = 0.0, lam = 0.0;
+    long long colfix = 0;
+    double lam = 0.0;
     int bad = 0;
     if (i < K.nx) {
-        const int ja = (int)blockIdx.y * H, jb = min(K.ny, ja + H);
-        for (int j = ja; j < jb; ++j) {
+        const int ja = (int)blockIdx.y * H, je = min(K.ny, ja + H);
+        for (int j = ja; j < je; ++j) {
             const size_t cidx = (size_t)j * K.nx + i;
             if (solid && solid[cidx]) continue;
-            const double q0 = Q[cidx], q1 = Q[plane + cidx], q2 = Q[2 * plane + cidx], q3 = Q[3 * plane + cidx];
-            const double q[4] = {q0, q1, q2, q3};
-            colsum += detector_term(K, q);
+            const double q[4] = {Q[cidx], Q[plane + cidx], Q[2 * plane + cidx], Q[3 * plane + cidx]};
+            colfix += __double2ll_rn(detector_term(K, q) * fix_scale);
             lam = fmax(lam, cfl_rate(K, q));
-            if (!(q0 > 0.0) || !(q3 > 0.0) || !isfinite(q0) || !isfinite(q1) || !isfinite(q2) || !isfinite(q3))
+            if (!(q[0] > 0.0) || !(q[3] > 0.0) || !isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[2]) ||
+                !isfinite(q[3]))
                 bad = 1;
         }
-        partial[(size_t)blockIdx.y * K.nx + i] = colsum;
+        if (colfix != 0) atomicAdd((unsigned long long *)&S[i], (unsigned long long)colfix);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -247,30 +582,47 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
     }
 }
 
-// Free-surface heights y0_i = y_L(i) + dy * sum of the column's partial sums (bottom to top), and
-// dt = CFL / max rate; the elapsed time advances by the dt of the step just taken.
-__global__ void finalize_kernel(const double *__restrict__ partial, int nseg, const int *__restrict__ jb,
-                                double *__restrict__ Y0, unsigned long long *lam_slot, int *flag, double *dt_dev,
-                                double *t_dev, double dt_used, int use_dev_dt, int advance_t, Consts K)
+// dt of a state given through bn_set_state, from reduce_kernel's CFL maximum.
+__global__ void init_dt_kernel(unsigned long long *lam_slot, int *flag, double *dt_out, Consts K)
 {
-    const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < K.nx) {
-        double s = 0.0;
-        for (int seg = 0; seg < nseg; ++seg) s += partial[(size_t)seg * K.nx + i];
-        Y0[i] = (K.ylo + jb[i] * K.dy) + K.dy * s;
-    }
-    if (i == 0) {
-        const double used = use_dev_dt ? *dt_dev : dt_used;
-        if (advance_t) *t_dev += used;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
         const double lam = __longlong_as_double((long long)*lam_slot);
         *lam_slot = 0ull;
         if (lam > 0.0 && isfinite(lam)) {
-            *dt_dev = K.cfl / lam;
+            *dt_out = K.cfl / lam;
         } else {
-            *dt_dev = 0.0;
+            *dt_out = 0.0;
             atomicOr(flag, 2);
         }
     }
+}
+
+// Schedule state of the next step after bn_set_state or a change of the launch shape: empty
+// descriptor list, uniform recorded costs (1 per row), cleared strip totals to accumulate into.
+__global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
+                                     double *Ts_in, double *Ts_acc, int nstrips, int ny)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < max_slots) desc[s] = 0ull;
+    if (s < (long long)nstrips * ny) cost[s] = 1.0f;
+    if (s < nstrips) {
+        Ts_in[s] = (double)ny;
+        Ts_acc[s] = 0.0;
+    }
+    if (s == 0) *nranges = R0;
+}
+
+__global__ void zero_kernel(long long *p, int n)
+{
+    const int s = (int)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) p[s] = 0;
+}
+
+// y0 = y_bottom + dy * integral per column, for bn_get_y0.
+__global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, double *y0, Consts K)
+{
+    const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < K.nx) y0[i] = (K.ylo + jb[i] * K.dy) + K.dy * ((double)S[i] * fix_inv);
 }
 
 }  // namespace bn

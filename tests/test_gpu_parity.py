@@ -44,9 +44,9 @@ def bn(torch_cuda):
     return bn2d
 
 
-def gpu_run(bn, torch, s, n_steps, rows=None, q0=None):
+def gpu_run(bn, torch, s, n_steps, rows=None, q0=None, waves=None):
     q0 = s.q if q0 is None else q0
-    with bn.Simulation(s, rows_per_block=rows) as sim:
+    with bn.Simulation(s, rows_per_block=rows, wavefronts=waves) as sim:
         sim.set_state(torch.from_numpy(np.ascontiguousarray(q0)).cuda())
         sim.run(n_steps)
         t, dt_next = sim.time()
@@ -94,14 +94,28 @@ def test_dam_break_200_steps(oracle, bn, torch_cuda):
     assert abs(dtg - dt_o) <= 1e-11 * dt_o
 
 
-@pytest.mark.parametrize("rows", [1, 3, 7, 16, 64])
-def test_ragged_grid_tilings(oracle, bn, torch_cuda, rows):
+@pytest.mark.parametrize("rows,waves", [(1, None), (3, None), (7, None), (16, None), (64, None),
+                                        (1, 1), (2, 3), (5, 2), (4, 5000)])
+def test_ragged_grid_tilings(oracle, bn, torch_cuda, rows, waves):
     """Sizes that are not multiples of the 60-column strip or the row block, an obstacle,
-    a noisy non-equilibrium state; every row-block height."""
+    a noisy non-equilibrium state; row-block heights from 1 to beyond the grid, and launches
+    from one wavefront (which must take every range itself) to more wavefronts than blocks."""
     s = sc.random_state(sc.dam_break(7, 67, 37), seed=3, amp=0.002, vel=0.02)
-    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 25, rows=rows)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 25, rows=rows, waves=waves)
     qo, to, dto = oracle.run(s, s.q, 25)
     assert_parity(s, qg, qo)
+
+
+def test_launch_shape_does_not_change_results(bn, torch_cuda):
+    """Work distribution (which wavefront marches which rows, splits, idle wavefronts) leaves
+    every bit of the state, the free surface, the elapsed time and the next dt unchanged."""
+    s = sc.random_state(sc.dam_break(5, 250, 130), seed=9, amp=0.002, vel=0.05)
+    ref = gpu_run(bn, torch_cuda, s, 60)
+    for rows, waves in [(1, 7), (3, 64), (8, 1), (4, 50000), (13, 333)]:
+        got = gpu_run(bn, torch_cuda, s, 60, rows=rows, waves=waves)
+        assert np.array_equal(got[0], ref[0]), (rows, waves)
+        assert got[1] == ref[1] and got[2] == ref[2], (rows, waves)
+        assert np.array_equal(got[3], ref[3]), (rows, waves)
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 40), (40, 1), (2, 2), (1, 1), (61, 5), (121, 3)])

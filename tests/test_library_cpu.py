@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_names_every_code():
     L = bn2d.lib()
-    for code in (0, -1, -2, -3, -4, -5, -99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
         assert L.bn_strerror(code)
 
 
@@ -74,4 +74,6 @@ def test_null_arguments():
     assert L.bn_run(None, 1) == bn2d.BN_EINVAL
     assert L.bn_set_state(None, None) == bn2d.BN_EINVAL
     assert L.bn_status(None) == bn2d.BN_EINVAL
+    assert L.bn_set_launch(None, 0, 0) == bn2d.BN_EINVAL
+    assert L.bn_get_launch(None, None, None) == bn2d.BN_EINVAL
     L.bn_destroy(None)
