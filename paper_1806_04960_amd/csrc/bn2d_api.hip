@@ -28,12 +28,10 @@ struct Control {
     const double *Ts_in;
     double *Ts_out;
     double *Ts_clear;
-    const double *dt_dev;
-    double *dt_out;
-    double *t;
-    unsigned long long *lam_acc;
+    const unsigned long long *lam_in;
+    unsigned long long *lam_out;
     unsigned long long *lam_clear;
-    int *done;
+    double *t;
     int *flag;
     int B;
     int ny;
@@ -49,13 +47,13 @@ struct StepArgs {
     unsigned long long kaddr;
     unsigned long long caddr;
     double dt_arg;
-    int use_dt_dev;
+    int cfl_dt;
     int nx, ny, B;
 };
 __global__ void step_kernel(StepArgs a);
 __global__ void reduce_kernel(const double *Q, const uint8_t *solid, long long *S, double fix_scale,
                               unsigned long long *lam_slot, int *flag, Consts K, int H);
-__global__ void init_dt_kernel(unsigned long long *lam_slot, int *flag, double *dt_out, Consts K);
+__global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K);
 __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
                                      double *Ts_in, double *Ts_acc, int nstrips, int ny);
 __global__ void zero_kernel(long long *p, int n);
@@ -94,10 +92,9 @@ struct Dev {
     float *cost = nullptr;               // [2][nstrips][ny] recorded march cost per row
     double *Ts = nullptr;                // [3][nstrips] recorded march cost per strip
     int *nranges = nullptr;              // [2]
-    unsigned long long *lam = nullptr;   // [2]
-    int *done = nullptr;
+    unsigned long long *lam = nullptr;   // [3] CFL rate maxima
     int *flag = nullptr;
-    double *dt = nullptr;                // [2]
+    double *dt = nullptr;                // dt query staging
     double *t = nullptr;
     bn::Consts *kc = nullptr;            // the physical constants, read by the step kernel
     bn::Control *ctl = nullptr;          // [6]: one per (slot parity, integral buffer) combination
@@ -187,12 +184,10 @@ int write_controls(bn_ctx *c)
             C.Ts_in = c->d.Ts + m * ns;
             C.Ts_out = c->d.Ts + ((m + 1) % 3) * ns;
             C.Ts_clear = c->d.Ts + ((m + 2) % 3) * ns;
-            C.dt_dev = c->d.dt + p;
-            C.dt_out = c->d.dt + q;
+            C.lam_in = c->d.lam + m;
+            C.lam_out = c->d.lam + (m + 1) % 3;
+            C.lam_clear = c->d.lam + (m + 2) % 3;
             C.t = c->d.t;
-            C.lam_acc = c->d.lam + q;
-            C.lam_clear = c->d.lam + p;
-            C.done = c->d.done;
             C.flag = c->d.flag;
             C.B = c->B;
             C.ny = c->grid.ny;
@@ -233,17 +228,14 @@ int zero_S(bn_ctx *c, int m)
 // is cleared for the next step's accumulation.
 int refresh_reductions(bn_ctx *c)
 {
-    const int p = c->par, m = c->m3;
+    const int m = c->m3;
     int rc = zero_S(c, m);
     if (!rc) rc = zero_S(c, (m + 1) % 3);
     if (rc) return rc;
     const int H = 64;
     const dim3 rgrid((c->grid.nx + 63) / 64, (c->grid.ny + H - 1) / H);
     hipLaunchKernelGGL(bn::reduce_kernel, rgrid, dim3(64), 0, c->stream, c->d.q[c->cur], c->d.solid,
-                       c->d.S + (size_t)m * c->grid.nx, c->fix_scale, c->d.lam + p, c->d.flag, c->K, H);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(bn::init_dt_kernel, dim3(1), dim3(64), 0, c->stream, c->d.lam + p, c->d.flag, c->d.dt + p,
-                       c->K);
+                       c->d.S + (size_t)m * c->grid.nx, c->fix_scale, c->d.lam + m, c->d.flag, c->K, H);
     HIP_TRY(hipGetLastError());
     return init_ranges(c);
 }
@@ -260,7 +252,7 @@ int launch_step(bn_ctx *c, bool device_dt, double dt_arg)
     a.kaddr = (unsigned long long)(uintptr_t)c->d.kc;
     a.caddr = (unsigned long long)(uintptr_t)(c->d.ctl + 3 * p + m);
     a.dt_arg = dt_arg;
-    a.use_dt_dev = device_dt ? 1 : 0;
+    a.cfl_dt = device_dt ? 1 : 0;
     a.nx = c->grid.nx;
     a.ny = c->grid.ny;
     a.B = c->B;
@@ -275,11 +267,19 @@ int launch_step(bn_ctx *c, bool device_dt, double dt_arg)
 void free_all(bn_ctx *c)
 {
     Dev &d = c->d;
-    void *ptrs[] = {d.q[0], d.q[1], d.solid, d.jb, d.S, d.y0, d.desc, d.cost, d.Ts, d.nranges, d.lam, d.done, d.flag,
+    void *ptrs[] = {d.q[0], d.q[1], d.solid, d.jb, d.S, d.y0, d.desc, d.cost, d.Ts, d.nranges, d.lam, d.flag,
                     d.dt, d.t, d.kc, d.ctl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = Dev();
+}
+
+// dt = CFL / max rate of the current state into d.dt (stream-ordered).
+int query_dt(bn_ctx *c)
+{
+    hipLaunchKernelGGL(bn::dt_kernel, dim3(1), dim3(64), 0, c->stream, c->d.lam + c->m3, c->d.dt, c->d.flag, c->K);
+    HIP_TRY(hipGetLastError());
+    return BN_OK;
 }
 
 int sync_flag(bn_ctx *c)
@@ -392,10 +392,9 @@ int bn_create(const bn_grid *grid, const bn_params *params, const uint8_t *solid
     ALLOC(c->d.Ts, sizeof(double) * 3 * (size_t)c->nstrips);
     ALLOC(c->d.y0, sizeof(double) * nx);
     ALLOC(c->d.nranges, sizeof(int) * 2);
-    ALLOC(c->d.lam, sizeof(unsigned long long) * 2);
-    ALLOC(c->d.done, sizeof(int));
+    ALLOC(c->d.lam, sizeof(unsigned long long) * 3);
     ALLOC(c->d.flag, sizeof(int));
-    ALLOC(c->d.dt, sizeof(double) * 2);
+    ALLOC(c->d.dt, sizeof(double));
     ALLOC(c->d.t, sizeof(double));
     ALLOC(c->d.kc, sizeof(bn::Consts));
     ALLOC(c->d.ctl, sizeof(bn::Control) * 6);
@@ -407,10 +406,9 @@ int bn_create(const bn_grid *grid, const bn_params *params, const uint8_t *solid
     if (rc) return fail(rc);
     e = hipMemcpy(c->d.jb, jb.data(), sizeof(int) * nx, hipMemcpyHostToDevice);
     if (e == hipSuccess && solid) e = hipMemcpy(c->d.solid, solid, plane, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(c->d.lam, 0, sizeof(unsigned long long) * 2);
-    if (e == hipSuccess) e = hipMemset(c->d.done, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->d.lam, 0, sizeof(unsigned long long) * 3);
     if (e == hipSuccess) e = hipMemset(c->d.flag, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(c->d.dt, 0, sizeof(double) * 2);
+    if (e == hipSuccess) e = hipMemset(c->d.dt, 0, sizeof(double));
     if (e == hipSuccess) e = hipMemset(c->d.t, 0, sizeof(double));
     if (e == hipSuccess) e = hipMemset(c->d.S, 0, sizeof(long long) * 3 * nx);
     if (e == hipSuccess) e = hipMemset(c->d.nranges, 0, sizeof(int) * 2);
@@ -432,7 +430,7 @@ int bn_set_state(bn_ctx *c, const double *q_dev)
     HIP_TRY(hipMemcpyAsync(c->d.q[c->cur], q_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->d.flag, 0, sizeof(int), c->stream));
     HIP_TRY(hipMemsetAsync(c->d.t, 0, sizeof(double), c->stream));
-    HIP_TRY(hipMemsetAsync(c->d.lam, 0, sizeof(unsigned long long) * 2, c->stream));
+    HIP_TRY(hipMemsetAsync(c->d.lam, 0, sizeof(unsigned long long) * 3, c->stream));
     int rc = refresh_reductions(c);
     if (rc) return rc;
     c->has_state = true;
@@ -450,7 +448,9 @@ int bn_get_state(bn_ctx *c, double *q_dev)
 int bn_compute_dt(bn_ctx *c, double *dt_host)
 {
     if (!c || !dt_host || !c->has_state) return BN_EINVAL;
-    HIP_TRY(hipMemcpyAsync(dt_host, c->d.dt + c->par, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    int rc = query_dt(c);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(dt_host, c->d.dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     return sync_flag(c);
 }
 
@@ -475,8 +475,10 @@ int bn_get_time(bn_ctx *c, double *t_host, double *next_dt_host)
     if (!c || !c->has_state) return BN_EINVAL;
     double tmp[2];
     HIP_TRY(hipMemcpyAsync(&tmp[0], c->d.t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(&tmp[1], c->d.dt + c->par, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    int rc = sync_flag(c);
+    int rc = query_dt(c);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(&tmp[1], c->d.dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    rc = sync_flag(c);
     if (t_host) *t_host = tmp[0];
     if (next_dt_host) *next_dt_host = tmp[1];
     return rc;

@@ -15,7 +15,8 @@
 // its duration per row; the next step cuts the strips into one range per wavefront of equal
 // recorded cost (second-order liquid rows cost about 1.5x first-order gas rows, rows across the
 // free surface more), so that all wavefronts finish together as long as the flow changes little
-// from one step to the next.  A strip head below the first cut is left unowned.  A wavefront
+// from one step to the next; a wavefront whose share crosses into the next strip also owns that
+// strip's head, which it marches second.  A wavefront
 // claims B rows of its range at a time with an atomic add on the range's descriptor, issued a
 // row ahead so that the claim does not stall the march, and keeps marching through consecutive
 // claims without repeating the halo.  When its range is exhausted it takes an unowned range or
@@ -26,10 +27,11 @@
 //
 // Reductions.  The free-surface integral of the next step (Sec. 3.5) is accumulated per column in
 // 64-bit fixed point with atomic adds, which makes it independent of the order in which rows are
-// processed and so of the schedule; the CFL rate is folded into a 64-bit atomic max.  The last
-// wavefront to finish turns the maximum rate into the next dt.  The fixed-point integrals are
-// triple-buffered (read, accumulate, clear for the next step), as are the per-strip cost totals;
-// dt, the CFL maximum, the per-row costs and the range lists are double-buffered, each step
+// processed and so of the schedule; the CFL rate is folded into a 64-bit atomic max, which the
+// next step turns into its dt.  Nothing at the end of a step waits for other wavefronts: every
+// result that crosses wavefronts is an atomic, read by the next launch.  The fixed-point
+// integrals, the CFL maxima and the per-strip cost totals are triple-buffered (read, accumulate,
+// clear for the next step); the per-row costs and the range lists are double-buffered, each step
 // clearing the next step's list.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,12 +57,10 @@ struct Control {
     const double *Ts_in;            // [nstrips] recorded cost per strip (previous step)
     double *Ts_out;                 // ... accumulated by this step
     double *Ts_clear;               // third buffer, zeroed for the next step
-    const double *dt_dev;           // dt of this step computed by the previous one (run mode)
-    double *dt_out;                 // CFL dt of Qn
+    const unsigned long long *lam_in;  // CFL rate maximum of Q (bits of a non-negative double)
+    unsigned long long *lam_out;    // ... of Qn (accumulated)
+    unsigned long long *lam_clear;  // third slot, zeroed for the next step
     double *t;                      // elapsed time
-    unsigned long long *lam_acc;    // CFL max of Qn (accumulated here)
-    unsigned long long *lam_clear;  // the other slot, zeroed for the next step
-    int *done;                      // finished wavefronts
     int *flag;                      // 1: non-physical state, 2: no CFL rate, 4: scheduler error
     int B;                          // rows per claim
     int ny;                         // rows per strip
@@ -77,7 +77,7 @@ struct StepArgs {
     unsigned long long kaddr;       // device address of the Consts
     unsigned long long caddr;       // device address of the Control
     double dt_arg;                  // dt of this step (explicit mode)
-    int use_dt_dev;                 // 1: take dt from Control::dt_dev
+    int cfl_dt;                     // 1: dt = CFL / max rate of Q, else dt_arg
     int nx, ny, B;
 };
 
@@ -130,32 +130,64 @@ __device__ __forceinline__ double wave_incl_scan(double v)
 }
 
 // For each target t[k]: the index i of v[0..n) with v[0] + ... + v[i-1] <= t[k] < v[0] + ... + v[i]
-// (n if there is none) and t[k] minus the lower bound.  Read in chunks of 64.
+// (n if there is none) and t[k] minus the lower bound.  Lane l sums the contiguous entries
+// [l m, (l+1) m), m = ceil(n / 64); one wave scan over the lane sums finds the lane holding the
+// target, which then walks its entries.  Every wavefront computing the same target on the same
+// data gets the same answer (the summation order is fixed).
 template <int NT, class T>
 __device__ void locate(const T *v, int n, const double (&t)[NT], int (&idx)[NT], double (&off)[NT])
 {
     const int lane = threadIdx.x;
+    const int m = (n + 63) / 64, b = min(lane * m, n), e = min(b + m, n);
+    // loads 16 at a time from clamped addresses (no branch, one wait per batch)
+    auto batch = [&](int c, double (&vv)[16]) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const double x = (double)v[min(c + u, n - 1)];
+            vv[u] = c + u < e ? x : 0.0;
+        }
+    };
+    double sum = 0.0;
+    for (int c = b; c < e; c += 16) {
+        double vv[16];
+        batch(c, vv);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += vv[u];
+    }
+    const double incl = wave_incl_scan(sum), excl = incl - sum;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         idx[k] = n;
         off[k] = 0.0;
-    }
-    double base = 0.0;
-    for (int c = 0; c < n; c += 64) {
-        const int i = c + lane;
-        const double val = i < n ? (double)v[i] : 0.0;
-        const double incl = base + wave_incl_scan(val), excl = incl - val;
+        const unsigned long long mask = __ballot(b < e && excl <= t[k] && t[k] < incl);
+        if (!mask) continue;
+        const int l = __ffsll((long long)mask) - 1;
+        // lane l walks its entries; the others follow along and discard
+        const int lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
+        const double lx = __shfl(excl, l, 64);
+        int found = le - 1;
+        double rem = 0.0, acc = lx;
+        bool done = false;
+        for (int c = lb; c < le && !done; c += 16) {
+            double vv[16];
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (idx[k] != n) continue;
-            const unsigned long long m = __ballot(i < n && excl <= t[k] && t[k] < incl);
-            if (m) {
-                const int l = __ffsll((long long)m) - 1;
-                idx[k] = c + l;
-                off[k] = t[k] - __shfl(excl, l, 64);
+            for (int u = 0; u < 16; ++u) {
+                const double x = (double)v[min(c + u, n - 1)];
+                vv[u] = c + u < le ? x : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double next = acc + vv[u];
+                if (!done && c + u < le && t[k] < next) {
+                    found = c + u;
+                    rem = t[k] - acc;
+                    done = true;
+                }
+                acc = next;
             }
         }
-        base = __shfl(incl, 63, 64);
+        idx[k] = found;
+        off[k] = rem;
     }
 }
 
@@ -453,7 +485,17 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs a)
     {
         const Consts &K = consts_at(ka);
         const Control &C = control_at(ca);
-        dt = a.use_dt_dev ? *C.dt_dev : a.dt_arg;
+        if (a.cfl_dt) {
+            const double lmax = __longlong_as_double((long long)*C.lam_in);
+            dt = (lmax > 0.0 && isfinite(lmax)) ? K.cfl / lmax : 0.0;
+        } else {
+            dt = a.dt_arg;
+        }
+        if (w == 0 && lane == 0) {
+            *C.t += dt;
+            *C.lam_clear = 0ull;
+            if (!(dt > 0.0)) atomicOr(C.flag, 2);
+        }
         dtdx = dt * K.inv_dx;
         dtdy = dt * K.inv_dy;
 
@@ -468,7 +510,8 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs a)
     int bad = 0;
 
     // ---- this wavefront's range: the cost interval [w, w+1) T/P of the recorded costs ---------
-    int strip = 0, j0 = 0, E = 0, slot = w;
+    int strip = 0, j0 = 0, E = 0, slot = w, head_strip = -1;
+    double head_off = 0.0;
     bool have = false;
     {
         const Control &C = control_at(ca);
@@ -477,72 +520,67 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs a)
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
         const double step = total / C.P;
-        const double xs[3] = {w > 0 ? (w - 1) * step : -1.0, w * step, w + 1 < C.P ? (w + 1) * step : total};
-        int sidx[3];
-        double soff[3];
-        locate<3>(C.Ts_in, C.nstrips, xs, sidx, soff);
-        const int s_prev = w > 0 ? sidx[0] : -1, s_w = sidx[1], s_next = sidx[2];
+        const double xs[2] = {w * step, w + 1 < C.P ? (w + 1) * step : total};
+        int sidx[2];
+        double soff[2];
+        locate<2>(C.Ts_in, C.nstrips, xs, sidx, soff);
+        const int s_w = sidx[0], s_next = sidx[1];
         if (s_w < C.nstrips) {
-            const double rt[2] = {soff[1], s_next == s_w ? soff[2] : 1e300};
+            const double rt[2] = {soff[0], s_next == s_w ? soff[1] : 1e300};
             int ridx[2];
             double roff[2];
             locate<2>(C.cost_in + (size_t)s_w * C.ny, C.ny, rt, ridx, roff);
             const int lo = ridx[0], hi = s_next == s_w ? ridx[1] : C.ny;
             // published with atomic stores: other wavefronts read and update them atomically
-            if (lane == 0) {
-                if (lo < hi) atomicExch(C.desc + w, d_make(true, s_w, hi, min(lo + a.B, hi)));
-                // the head of the first strip this wavefront cuts, and strips it spans whole, unowned
-                if (s_prev < s_w && lo > 0) atomicExch(C.desc + C.P + s_w, d_make(false, s_w, lo, 0));
-            }
-            for (int s = s_w + 1 + lane; s < s_next && s < C.nstrips; s += 64)
-                atomicExch(C.desc + C.P + s, d_make(false, s, C.ny, 0));
+            if (lane == 0 && lo < hi) atomicExch(C.desc + w, d_make(true, s_w, hi, min(lo + a.B, hi)));
             if (lo < hi) {
                 have = true;
                 strip = s_w;
                 j0 = lo;
                 E = min(lo + a.B, hi);
             }
+            // strips the share spans whole are left unowned (rare: a strip cheaper than a share)
+            for (int s = s_w + 1 + lane; s < s_next && s < C.nstrips; s += 64)
+                atomicExch(C.desc + C.P + s, d_make(false, s, C.ny, 0));
+            // the head of the strip the share ends in is this wavefront's too: published owned and
+            // unclaimed once its extent is known (after the first range is marched)
+            if (s_next > s_w && s_next < C.nstrips) {
+                head_strip = s_next;
+                head_off = soff[1];
+            }
         }
-        __threadfence();
     }
-    if (!have) have = steal(ca, a.B, &strip, &j0, &E, &slot);
+    if (have) march(a, ka, ca, sq, sf, strip, j0, E, slot, dt, dtdx, dtdy, lam, bad);
+    if (head_strip >= 0) {
+        const Control &C = control_at(ca);
+        const double ht[1] = {head_off};
+        int hidx[1];
+        double hoff[1];
+        locate<1>(C.cost_in + (size_t)head_strip * C.ny, C.ny, ht, hidx, hoff);
+        const int hend = hidx[0];
+        if (hend > 0) {
+            // nobody else can know this range yet: it is claimed directly and then published
+            const int e0 = min(a.B, hend);
+            if (lane == 0) atomicExch(C.desc + C.P + head_strip, d_make(true, head_strip, hend, e0));
+            march(a, ka, ca, sq, sf, head_strip, 0, e0, C.P + head_strip, dt, dtdx, dtdy, lam, bad);
+        }
+    }
+    have = steal(ca, a.B, &strip, &j0, &E, &slot);
     while (have) {
         march(a, ka, ca, sq, sf, strip, j0, E, slot, dt, dtdx, dtdy, lam, bad);
         have = steal(ca, a.B, &strip, &j0, &E, &slot);
     }
 
-    // ---- CFL max and non-physical flag; the last wavefront computes the next dt ---------------
+    // ---- CFL maximum and non-physical flag ------------------------------------------------------
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         lam = fmax(lam, __shfl_xor(lam, off, 64));
         bad |= __shfl_xor(bad, off, 64);
     }
-    const Control &C = control_at(ca);
-    __threadfence();
-    int prior = 0;
     if (lane == 0) {
-        if (lam > 0.0) atomicMax(C.lam_acc, (unsigned long long)__double_as_longlong(lam));
+        const Control &C = control_at(ca);
+        if (lam > 0.0) atomicMax(C.lam_out, (unsigned long long)__double_as_longlong(lam));
         if (bad) atomicOr(C.flag, 1);
-        __threadfence();
-        prior = atomicAdd(C.done, 1);
-    }
-    prior = __shfl(prior, 0, 64);
-    if (prior != C.P - 1) return;
-
-    if (lane == 0) {
-        const Consts &K = consts_at(ka);
-        __threadfence();
-        const double lmax = __longlong_as_double(
-            (long long)__hip_atomic_load(C.lam_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        *C.t += dt;
-        if (lmax > 0.0 && isfinite(lmax)) {
-            *C.dt_out = K.cfl / lmax;
-        } else {
-            *C.dt_out = 0.0;
-            atomicOr(C.flag, 2);
-        }
-        *C.lam_clear = 0ull;
-        *C.done = 0;
     }
 }
 
@@ -582,18 +620,14 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
     }
 }
 
-// dt of a state given through bn_set_state, from reduce_kernel's CFL maximum.
-__global__ void init_dt_kernel(unsigned long long *lam_slot, int *flag, double *dt_out, Consts K)
+// dt = CFL / max rate of the current state, for the host (bn_compute_dt, bn_get_time).
+__global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const double lam = __longlong_as_double((long long)*lam_slot);
-        *lam_slot = 0ull;
-        if (lam > 0.0 && isfinite(lam)) {
-            *dt_out = K.cfl / lam;
-        } else {
-            *dt_out = 0.0;
-            atomicOr(flag, 2);
-        }
+        const bool ok = lam > 0.0 && isfinite(lam);
+        *dt_out = ok ? K.cfl / lam : 0.0;
+        if (!ok) atomicOr(flag, 2);
     }
 }
 
