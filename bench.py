@@ -76,6 +76,19 @@ def cpu_baseline(s, steps):
                       f"({el:.1f} s, 1 thread)"}
 
 
+def copy_probe(nbytes):
+    """A plain copy of known size, 5 times: FETCH_SIZE and WRITE_SIZE read for it give the scale
+    of those counters (bytes counted per byte moved) used for the step kernel's HBM traffic."""
+    import torch
+    n = nbytes // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,7 +99,12 @@ def main():
     ap.add_argument("--wavefronts", type=int, default=None, help="wavefronts of the persistent step kernel")
     ap.add_argument("--cpu-baseline-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run device-to-device copies of BYTES bytes (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would own a strip "
@@ -114,6 +132,9 @@ def main():
         dt_start = sim.compute_dt()
         sim.run(args.warmup)
         sim.status()
+        # timed region: K steps, one kernel launch each, back to back on the stream the kernel
+        # runs on (the context uses torch's current stream); the average launch duration is the
+        # region's duration over K
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record()
@@ -121,6 +142,7 @@ def main():
         end.record()
         torch.cuda.synchronize()
         ms = start.elapsed_time(end)
+        launch_ms = ms / args.steps
         sim.status()
         q_end = sim.get_state().cpu().numpy()
         y0_end = sim.y0()
@@ -134,12 +156,12 @@ def main():
     f0 = flops.count(s, s.q, y0_start, dt_start)
     f1 = flops.count(s, q_end, y0_end, dt_end)
     flops_per_launch = 0.5 * (f0["total"] + f1["total"])
-    achieved = flops_per_launch / (ms_per_step / 1e3)
+    achieved = flops_per_launch / (launch_ms / 1e3)
     traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                "flops_per_cell_update": flops_per_launch / cells,
-                "hbm_frac_at_algorithmic_bytes": cells * STATE_BYTES_PER_CELL / (ms_per_step / 1e3) / PEAK_HBM}
+                "flops_per_cell_update": flops_per_launch / cells, "kernel_ms": launch_ms,
+                "hbm_frac_at_algorithmic_bytes": cells * STATE_BYTES_PER_CELL / (launch_ms / 1e3) / PEAK_HBM}
 
     line = {
         "metric": "FP64 cell updates/sec",

@@ -63,18 +63,19 @@ __global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, dou
 namespace {
 
 constexpr int kOutCols = 60;  // output columns per wavefront (64 lanes minus a 2-column halo each side)
-constexpr int kDefaultRowsPerBlock = 4;
-constexpr int kSimdsPerCU = 4;  // CDNA compute unit
+constexpr int kDefaultRowsPerBlock = 32;
 
-// One wavefront per SIMD: a second resident wavefront of this kernel slows the first more than it
-// adds, so the persistent launch fills every SIMD once.
+// As many wavefronts as the device holds at once (compute units x resident single-wavefront
+// workgroups per unit, from the kernel's register use): the launch is persistent.
 int default_wavefronts()
 {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                 hipSuccess || cus <= 0)
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bn::step_kernel, 64, 0) != hipSuccess || cus <= 0 ||
+        per_cu <= 0)
         return 1024;
-    return cus * kSimdsPerCU;
+    return cus * per_cu;
 }
 
 thread_local std::string g_last_hip_error;
@@ -111,7 +112,7 @@ struct bn_ctx {
     int cur = 0;       // state buffer holding the current state
     int par = 0;       // slot of dt / CFL maximum / range list read by the next step
     int m3 = 0;        // fixed-point buffer holding the current state's free-surface integral
-    int B = 4;         // rows per block
+    int B = 32;        // rows per claim
     int P = 1024;      // wavefronts per launch
     int P_default = 1024;
     int nstrips = 0, R0 = 0, max_slots = 0, slots_alloc = 0;

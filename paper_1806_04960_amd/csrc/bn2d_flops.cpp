@@ -34,6 +34,7 @@ inline Counted &operator+=(Counted &a, Counted b) { a = a + b; return a; }
 inline bool operator>(Counted a, Counted b) { return a.v > b.v; }
 inline bool operator<(Counted a, Counted b) { return a.v < b.v; }
 inline bool operator!=(Counted a, Counted b) { return a.v != b.v; }
+inline bool operator==(Counted a, Counted b) { return a.v == b.v; }
 inline Counted fabs(Counted a) { return Counted(std::fabs(a.v)); }
 inline Counted fmin(Counted a, Counted b) { return Counted(std::fmin(a.v, b.v)); }
 inline Counted fmax(Counted a, Counted b) { return Counted(std::fmax(a.v, b.v)); }

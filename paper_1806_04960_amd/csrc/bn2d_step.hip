@@ -11,8 +11,9 @@
 // reconstruct).  A range that starts at row j0 first reconstructs row j0 - 1 (halo below) and
 // ends by reconstructing the row above its last one (halo above).
 //
-// Scheduling.  The launch is persistent: one wavefront per SIMD.  Every marched range records
-// its duration per row; the next step cuts the strips into one range per wavefront of equal
+// Scheduling.  The launch is persistent: as many wavefronts as the device holds at once (two per
+// SIMD at this kernel's register use).  Every marched range records its duration per row; the
+// next step cuts the strips into one range per wavefront of equal
 // recorded cost (second-order liquid rows cost about 1.5x first-order gas rows, rows across the
 // free surface more), so that all wavefronts finish together as long as the flow changes little
 // from one step to the next; a wavefront whose share crosses into the next strip also owns that
