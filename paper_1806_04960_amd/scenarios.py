@@ -174,6 +174,20 @@ def dam_break(seed: int = 0, nx: int = 2048, ny: int = 1024) -> Scenario:
     return _fill(s, _rect(s, 0.0, W, 0.0, H))
 
 
+def weir(nx: int = 800, ny: int = 250) -> Scenario:
+    """Flow over a sharp-crested weir (Sec. 5.5 set-up): [-7.5, 7.5] x [0, 2.1], a one-cell-thick
+    solid strip of height 0.7 in the first column right of x = 0, liquid (alpha = 1 - eps) at rest
+    in [-7.5, 0] x [0, 1.5] with the hydrostatic density, dry (gas) right of the weir, k0 = 6.54e5,
+    reflective walls.  The paper's 800 x 250 mesh by default."""
+    s = Scenario("weir", nx, ny, -7.5, 7.5, 0.0, 2.1, k0=6.54e5, steps=0)
+    solid = np.zeros((ny, nx), np.uint8)
+    iw = int(np.searchsorted(s.xc(), 0.0))      # first cell whose centre is right of x = 0
+    solid[s.yc() <= 0.7, iw] = 1
+    s.solid = solid
+    s.meta = {"weir_column": iw, "crest": 0.7}
+    return _fill(s, _rect(s, -7.5, 0.0, 0.0, 1.5))
+
+
 def elliptic_drop(seed: int = 0, nx: int = 4096, ny: int = 4096) -> Scenario:
     """Oscillating elliptical drop without gravity on [-1, 1]^2 (Sec. 5.2 set-up, rescaled):
     semi-axes 0.5 (1 + da) along x and 0.25 (1 + db) along y, d ~ U[-0.02, 0.02];
