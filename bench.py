@@ -89,12 +89,95 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": n * 8, "launches": 5}), flush=True)
 
 
+def ensemble_main(args):
+    """A batch of uneven dam breaks (sizes 256x128 .. 1024x512, seed 0) advanced together, one
+    launch per step, each member with its own CFL step; against the same members run one after
+    another as single grids for the same number of steps."""
+    import numpy as np
+    import torch
+
+    from paper_1806_04960_amd import bn2d, flops
+    from paper_1806_04960_amd import scenarios as sc
+
+    members = sc.ensemble(0, args.members)
+    cells = sum(s.nx * s.ny for s in members)
+    print(f"# ensemble of {len(members)} members, {cells} cells, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    with bn2d.Batch(members, rows_per_block=args.rows, wavefronts=args.wavefronts) as b:
+        for k, s in enumerate(members):
+            b.set_state(k, torch.from_numpy(s.q).cuda())
+        rows, waves = b.launch()
+        start_info = [(b.y0(k), b.time(k)[1]) for k in range(len(members))]
+        b.run(args.warmup)
+        b.status()
+        start, end = ev(), ev()
+        torch.cuda.synchronize()
+        start.record()
+        b.run(args.steps)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        b.status()
+        end_info = [(b.get_state(k).cpu().numpy(), b.y0(k), b.time(k)[1]) for k in range(len(members))]
+    print(f"# batch: {ms / args.steps:.4f} ms per step", file=sys.stderr, flush=True)
+
+    # the same members one after another, each as a single grid, the same number of steps
+    seq_ms = 0.0
+    for s in members:
+        with bn2d.Simulation(s, rows_per_block=args.rows, wavefronts=args.wavefronts) as sim:
+            sim.set_state(torch.from_numpy(s.q).cuda())
+            sim.run(args.warmup)
+            start, end = ev(), ev()
+            torch.cuda.synchronize()
+            start.record()
+            sim.run(args.steps)
+            end.record()
+            torch.cuda.synchronize()
+            seq_ms += start.elapsed_time(end)
+            sim.status()
+    print(f"# sequential: {seq_ms / args.steps:.4f} ms per step of all members", file=sys.stderr, flush=True)
+
+    launch_ms = ms / args.steps
+    f = 0.0
+    for s, (y0a, dta), (qe, y0e, dte) in zip(members, start_info, end_info):
+        f += 0.5 * (flops.count(s, s.q, y0a, dta)["total"] + flops.count(s, qe, y0e, dte)["total"])
+    achieved = f / (launch_ms / 1e3)
+    line = {
+        "metric": "FP64 cell updates/sec",
+        "value": cells * args.steps / (ms / 1e3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": launch_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble of {len(members)} uneven dam breaks (256x128..1024x512, seed 0), "
+                               f"one launch per step", "members": len(members), "cells": cells,
+                   "rows_per_block": rows, "wavefronts": waves},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                     "flops_per_cell_update": f / cells, "kernel_ms": launch_ms},
+        "sequential": {"value": cells * args.steps / (seq_ms / 1e3), "ms_per_step": seq_ms / args.steps,
+                       "speedup_of_batch": seq_ms / ms},
+    }
+    if not args.no_cpu_baseline and args.cpu_baseline_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(members[0], args.cpu_baseline_steps)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="dam_break", choices=["dam_break", "elliptic_drop", "dam_break_small"])
+    ap.add_argument("--workload", default="dam_break",
+                    choices=["dam_break", "elliptic_drop", "dam_break_small", "ensemble"])
+    ap.add_argument("--members", type=int, default=64, help="ensemble size (workload ensemble)")
     ap.add_argument("--rows", type=int, default=None, help="rows per claimed block of the step kernel")
     ap.add_argument("--wavefronts", type=int, default=None, help="wavefronts of the persistent step kernel")
     ap.add_argument("--cpu-baseline-steps", type=int, default=4)
@@ -120,6 +203,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "ensemble":
+        ensemble_main(args)
+        return
     s = build_workload(args.workload)
     print(f"# workload {s.name} {s.nx}x{s.ny}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
           flush=True)

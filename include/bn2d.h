@@ -112,6 +112,43 @@ int bn_get_launch(bn_ctx *ctx, int32_t *rows_per_block, int32_t *wavefronts);
 void bn_destroy(bn_ctx *ctx);
 const char *bn_strerror(int code);
 
+/* ---- Batches: many grids advanced by one launch per step -------------------------------------
+ * A batch holds `count` independent grids (members) of any sizes, parameters and masks, e.g. an
+ * ensemble of scenarios too small to fill the device one by one.  Every bn_batch_run step advances
+ * each member by one explicit step of the scheme (the same step as bn_step) with its own CFL time
+ * step, in one launch of the step kernel whose work list spans all members.  Each member's results
+ * are bitwise those of a single-grid context on the same input.  A single-grid context is a batch
+ * of one.  Members are numbered 0..count-1.  Same ownership, error and stream rules as above. */
+typedef struct bn_batch bn_batch;
+
+/* grids[count], params[count]; solids: NULL or an array of count host masks (each NULL or nx*ny
+ * bytes, as for bn_create).  count in 1..32767, at most 32767 column strips of 60 in total. */
+int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params, const uint8_t *const *solids,
+                    void *hip_stream, bn_batch **out);
+
+/* Set / read member `member`'s state (device buffers as for bn_set_state / bn_get_state).  Every
+ * member needs a state before bn_batch_run.  Setting a state resets that member's time. */
+int bn_batch_set_state(bn_batch *batch, int32_t member, const double *q_dev);
+int bn_batch_get_state(bn_batch *batch, int32_t member, double *q_dev);
+
+/* n_steps >= 0 steps of every member, each with its own CFL time step.  Asynchronous. */
+int bn_batch_run(bn_batch *batch, int32_t n_steps);
+
+/* Elapsed time of a member and the dt its next step will use; free-surface heights of a member
+ * (nx doubles, host).  Synchronise. */
+int bn_batch_get_time(bn_batch *batch, int32_t member, double *t_host, double *next_dt_host);
+int bn_batch_get_y0(bn_batch *batch, int32_t member, double *y0_host);
+
+/* Synchronise; BN_ENONPHYS with *member set to the first member that met a non-physical state
+ * (member may be NULL; -1 when all are fine). */
+int bn_batch_status(bn_batch *batch, int32_t *member);
+
+/* Launch shape, as bn_set_launch / bn_get_launch. */
+int bn_batch_set_launch(bn_batch *batch, int32_t rows_per_block, int32_t wavefronts);
+int bn_batch_get_launch(bn_batch *batch, int32_t *rows_per_block, int32_t *wavefronts);
+
+void bn_batch_destroy(bn_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

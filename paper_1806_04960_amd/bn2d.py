@@ -17,7 +17,9 @@ BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
            "bn_get_time", "bn_get_y0", "bn_status", "bn_set_launch", "bn_get_launch", "bn_destroy",
-           "bn_strerror")
+           "bn_strerror", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
+           "bn_batch_get_time", "bn_batch_get_y0", "bn_batch_status", "bn_batch_set_launch",
+           "bn_batch_get_launch", "bn_batch_destroy")
 
 
 class BnError(RuntimeError):
@@ -64,8 +66,21 @@ def lib():
         L.bn_destroy.restype = None
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
+        i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+        L.bn_batch_create.argtypes = [i32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
+                                      ctypes.POINTER(ctypes.POINTER(ctypes.c_uint8)), vp, ctypes.POINTER(vp)]
+        L.bn_batch_set_state.argtypes = [vp, i32, vp]
+        L.bn_batch_get_state.argtypes = [vp, i32, vp]
+        L.bn_batch_run.argtypes = [vp, i32]
+        L.bn_batch_get_time.argtypes = [vp, i32, dp, dp]
+        L.bn_batch_get_y0.argtypes = [vp, i32, dp]
+        L.bn_batch_status.argtypes = [vp, pi32]
+        L.bn_batch_set_launch.argtypes = [vp, i32, i32]
+        L.bn_batch_get_launch.argtypes = [vp, pi32, pi32]
+        L.bn_batch_destroy.argtypes = [vp]
+        L.bn_batch_destroy.restype = None
         for name in SYMBOLS:
-            if name not in ("bn_destroy", "bn_strerror"):
+            if name not in ("bn_destroy", "bn_strerror", "bn_batch_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -166,6 +181,98 @@ class Simulation:
         if getattr(self, "_ctx", None):
             lib().bn_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """A batch of independent grids advanced together (``bn_batch_*``): one launch per step,
+    each member with its own CFL time step.  ``scenarios`` is a list of scenario objects as for
+    ``Simulation``."""
+
+    def __init__(self, scenarios, stream=None, rows_per_block: int | None = None, wavefronts: int | None = None):
+        import numpy as np
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        n = len(scenarios)
+        self.shapes = [(int(s.ny), int(s.nx)) for s in scenarios]
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        grids = (Grid * n)(*[grid_of(s) for s in scenarios])
+        params = (Params * n)(*[params_of(s) for s in scenarios])
+        self._solid_keep = []
+        solids = (ctypes.POINTER(ctypes.c_uint8) * n)()
+        for k, s in enumerate(scenarios):
+            if getattr(s, "solid", None) is not None:
+                m = np.ascontiguousarray(s.solid, dtype=np.uint8)
+                self._solid_keep.append(m)
+                solids[k] = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        b = ctypes.c_void_p()
+        check(lib().bn_batch_create(n, grids, params, solids, ctypes.c_void_p(self._stream.cuda_stream),
+                                    ctypes.byref(b)), "bn_batch_create")
+        self._b = b
+        if rows_per_block is not None or wavefronts is not None:
+            check(lib().bn_batch_set_launch(self._b, int(rows_per_block or 0), int(wavefronts or 0)),
+                  "bn_batch_set_launch")
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def set_state(self, member: int, q):
+        import torch
+        ny, nx = self.shapes[member]
+        if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and tuple(q.shape) == (4, ny, nx)):
+            raise ValueError("state must be a contiguous float64 CUDA tensor of shape [4, ny, nx]")
+        check(lib().bn_batch_set_state(self._b, int(member), ctypes.c_void_p(q.data_ptr())), "bn_batch_set_state")
+
+    def get_state(self, member: int):
+        import torch
+        ny, nx = self.shapes[member]
+        out = torch.empty((4, ny, nx), dtype=torch.float64, device="cuda")
+        check(lib().bn_batch_get_state(self._b, int(member), ctypes.c_void_p(out.data_ptr())), "bn_batch_get_state")
+        return out
+
+    def run(self, n_steps: int):
+        check(lib().bn_batch_run(self._b, int(n_steps)), "bn_batch_run")
+
+    def time(self, member: int):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        check(lib().bn_batch_get_time(self._b, int(member), ctypes.byref(t), ctypes.byref(dt)), "bn_batch_get_time")
+        return t.value, dt.value
+
+    def y0(self, member: int):
+        import numpy as np
+        out = np.zeros(self.shapes[member][1])
+        check(lib().bn_batch_get_y0(self._b, int(member), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "bn_batch_get_y0")
+        return out
+
+    def status(self):
+        m = ctypes.c_int32(-1)
+        code = lib().bn_batch_status(self._b, ctypes.byref(m))
+        if code != BN_OK:
+            raise BnError(code, f"bn_batch_status (member {m.value})", lib().bn_strerror(code).decode())
+
+    def launch(self):
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().bn_batch_get_launch(self._b, ctypes.byref(r), ctypes.byref(w)), "bn_batch_get_launch")
+        return r.value, w.value
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().bn_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

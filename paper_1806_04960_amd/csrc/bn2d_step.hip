@@ -1,6 +1,10 @@
 // Fused explicit step of the well-balanced Osher-Romberg scheme (Gaburro, Castro, Dumbser,
 // arXiv:1806.04960, Sec. 3) for gfx950, FP64 on the vector ALUs.
 //
+// Batch.  One launch advances every member of a batch of grids (any sizes, parameters and
+// masks; a single grid is a batch of one) by one step, each with its own time step.  The members'
+// column strips are concatenated into one list of strips that the scheduling below distributes.
+//
 // Marching.  A wavefront (64 lanes) works on a strip of 64 columns, lane L holding column
 // 60 s - 2 + L of strip s, and marches upwards through a range of rows.  Per row it loads one row
 // of the state (coalesced, 8 bytes per lane and plane, prefetched one row ahead), keeps the last
@@ -37,60 +41,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "bn2d_physics.h"
+#include "bn2d_layout.h"
 
 namespace bn {
 
-// Everything the step needs besides the hot pointers, for one combination of buffer rotations.
-// It lives in device memory and is read through the scalar cache at the few places it is used.
-struct Control {
-    const int *jb;                  // first fluid row of each column
-    const long long *S_in;          // fixed-point free-surface integral of Q (read)
-    long long *S_out;               // ... of Qn (accumulated)
-    long long *S_clear;             // third buffer, zeroed for the next step
-    double fix_scale, fix_inv;      // fixed-point scale 2^f and 2^-f
-    unsigned long long *desc;       // range descriptors of this step
-    int *nranges;                   // published descriptors of this step
-    unsigned long long *desc_next;  // range descriptors of the next step (initialised here)
-    int *nranges_next;
-    const float *cost_in;           // [nstrips][ny] recorded cost per row (previous step)
-    float *cost_out;                // ... recorded by this step
-    const double *Ts_in;            // [nstrips] recorded cost per strip (previous step)
-    double *Ts_out;                 // ... accumulated by this step
-    double *Ts_clear;               // third buffer, zeroed for the next step
-    const unsigned long long *lam_in;  // CFL rate maximum of Q (bits of a non-negative double)
-    unsigned long long *lam_out;    // ... of Qn (accumulated)
-    unsigned long long *lam_clear;  // third slot, zeroed for the next step
-    double *t;                      // elapsed time
-    int *flag;                      // 1: non-physical state, 2: no CFL rate, 4: scheduler error
-    int B;                          // rows per claim
-    int ny;                         // rows per strip
-    int nstrips;                    // column strips
-    int R0;                         // initial descriptors: one per wavefront, one head per strip
-    int max_slots;                  // descriptor capacity (initial descriptors and splits)
-    int P;                          // wavefronts of the launch
-};
-
-struct StepArgs {
-    const double *Q;                // state at t^n
-    double *Qn;                     // state at t^{n+1}
-    const uint8_t *solid;           // nx*ny mask or null
-    unsigned long long kaddr;       // device address of the Consts
-    unsigned long long caddr;       // device address of the Control
-    double dt_arg;                  // dt of this step (explicit mode)
-    int cfl_dt;                     // 1: dt = CFL / max rate of Q, else dt_arg
-    int nx, ny, B;
-};
-
-// The physical constants and the Control are read through an address the compiler must treat as
-// new at every use site (an empty asm that "modifies" it), so their scalar loads are repeated
-// where needed instead of being held in scalar registers across the march.
-typedef const __attribute__((address_space(4))) Consts *ConstsPtr;
+// Members and the Control are read through an address the compiler must treat as new at every use
+// site (an empty asm that "modifies" it), so their scalar loads are repeated where needed instead
+// of being held in scalar registers across the march.
+typedef const __attribute__((address_space(4))) Member *MemberPtr;
 typedef const __attribute__((address_space(4))) Control *ControlPtr;
-__device__ __forceinline__ const Consts &consts_at(unsigned long long addr)
+__device__ __forceinline__ const Member &member_at(unsigned long long base, int b)
 {
+    // b is the same in every lane (the compiler cannot always see it): take lane 0's
+    unsigned long long addr = base + (unsigned long long)__builtin_amdgcn_readfirstlane(b) * sizeof(Member);
     asm volatile("" : "+s"(addr));
-    return *(const Consts *)(ConstsPtr)addr;
+    return *(const Member *)(MemberPtr)addr;
 }
 __device__ __forceinline__ const Control &control_at(unsigned long long addr)
 {
@@ -202,23 +167,51 @@ struct LdsStencil {
     __device__ __forceinline__ int f(int dj, int di) const { return sf[s[dj]][lane + di - 1]; }
 };
 
-// March strip `strip` upwards from row j0, rows [j0, E) already claimed, claiming further rows
-// through descriptor `slot` (none if slot < 0) until a claim fails.
-__device__ void march(const StepArgs &a, unsigned long long ka, unsigned long long ca, double (*sq)[4][64],
-                      int (*sf)[64], int strip, int j0, int E, int slot, double dt, double dtdx, double dtdy,
-                      double &lam, int &bad)
+// The time step of member b for this launch.
+__device__ double member_dt(const StepArgs &a, unsigned long long ma, int b)
+{
+    if (!a.cfl_dt) return a.dt_arg;
+    const Member &M = member_at(ma, b);
+    const double lmax = __longlong_as_double((long long)*M.lam[a.m3]);
+    return (lmax > 0.0 && isfinite(lmax)) ? M.K.cfl / lmax : 0.0;
+}
+
+// March global strip g (member b, its strip `strip`) upwards from row j0, rows [j0, E) already
+// claimed, claiming further rows through descriptor `slot` (none if slot < 0) until a claim fails.
+__device__ void march(const StepArgs &a, unsigned long long ma, unsigned long long ca, double (*sq)[4][64],
+                      int (*sf)[64], int b, int g, int strip, int j0, int E, int slot)
 {
     const int lane = threadIdx.x;
+    int nx, ny;
+    const double *Qp;
+    double *Qnp;
+    const uint8_t *solid;
+    {
+        const Member &M = member_at(ma, b);
+        nx = M.K.nx;
+        ny = M.K.ny;
+        Qp = M.q[a.cur];
+        Qnp = M.q[1 - a.cur];
+        solid = M.solid;
+    }
+    const double dt = member_dt(a, ma, b);
+    double dtdx, dtdy;
+    {
+        const Consts &K = member_at(ma, b).K;
+        dtdx = dt * K.inv_dx;
+        dtdy = dt * K.inv_dy;
+    }
+    double lam = 0.0;
+    int bad = 0;
     const int i = strip * 60 - 2 + lane;
-    const bool colin = i >= 0 && i < a.nx;
+    const bool colin = i >= 0 && i < nx;
     const bool out_lane = colin && lane >= 2 && lane < 62;
     const bool rec_lane = lane >= 1 && lane <= 62;
-    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t plane = (size_t)nx * ny;
     double y0c = 0.0;
     if (colin) {
-        const Consts &K = consts_at(ka);
-        const Control &C = control_at(ca);
-        y0c = (K.ylo + C.jb[i] * K.dy) + K.dy * ((double)C.S_in[i] * C.fix_inv);
+        const Member &M = member_at(ma, b);
+        y0c = (M.K.ylo + M.jb[i] * M.K.dy) + M.K.dy * ((double)M.S[a.m3][i] * M.fix_inv);
     }
     unsigned long long *desc = slot >= 0 ? control_at(ca).desc + slot : nullptr;
     bool outstanding = false, last = slot < 0;
@@ -238,17 +231,17 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
     // (the address is clamped into the grid and the value replaced outside it, so that the load
     // needs no branch)
     auto load_row = [&](int r) {
-        const bool in = colin && r >= 0 && r < a.ny;
-        const size_t cidx = (size_t)min(max(r, 0), a.ny - 1) * a.nx + min(max(i, 0), a.nx - 1);
+        const bool in = colin && r >= 0 && r < ny;
+        const size_t cidx = (size_t)min(max(r, 0), ny - 1) * nx + min(max(i, 0), nx - 1);
         bool fluid = in;
-        if (a.solid) fluid = fluid && a.solid[cidx] == 0;
+        if (solid) fluid = fluid && solid[cidx] == 0;
         const double dflt[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double v = a.Q[k * plane + cidx];
+            const double v = Qp[k * plane + cidx];
             lq[k] = in ? v : dflt[k];
         }
-        lf = cell_flags(i, r, a.nx, a.ny, consts_at(ka).bc, fluid);
+        lf = cell_flags(i, r, nx, ny, member_at(ma, b).K.bc, fluid);
     };
     load_row(j0 - 2);
 
@@ -285,7 +278,7 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
         const bool fl = rec_lane && (fc_mid & F_FLUID);
         Rec rc;
         if (fl) {
-            const Consts &K = consts_at(ka);
+            const Consts &K = member_at(ma, b).K;
             LdsStencil st{sq, sf, {s_lo, s_mid, s_hi}, lane};
             reconstruct(K, st, jr, y0c, dt, rc);
         } else {
@@ -304,7 +297,7 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
         // cell is not needed compute on benign copies and discard the result. -----------------
         double X[4] = {0, 0, 0, 0};
         if (jr_inside) {
-            const Consts &K = consts_at(ka);
+            const Consts &K = member_at(ma, b).K;
             double qWr[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) qWr[k] = shfl_from_right(rc.qW[k]);
@@ -330,7 +323,7 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
         // ---- y-edge between row jr-1 (pending north state) and row jr ----------------------
         double DyM[4] = {0, 0, 0, 0}, DyP[4] = {0, 0, 0, 0};
         if (r > j0) {
-            const Consts &K = consts_at(ka);
+            const Consts &K = member_at(ma, b).K;
             const bool bf = rec_lane && (nF & F_FLUID);
             double qm[4], qp[4];
 #pragma unroll
@@ -347,16 +340,16 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
 
         // ---- finish row jr-1 ---------------------------------------------------------------
         const int jf = jr - 1;
-        if (jf >= j0 && jf < a.ny && out_lane) {
-            const Consts &K = consts_at(ka);
-            const Control &C = control_at(ca);
-            const size_t cidx = (size_t)jf * a.nx + i;
+        if (jf >= j0 && jf < ny && out_lane) {
+            const Member &M = member_at(ma, b);
+            const Consts &K = M.K;
+            const size_t cidx = (size_t)jf * nx + i;
             const bool fluid = sf[s_lo][lane] & F_FLUID;  // solid cells keep their values
             double qn[4];
             update_finish(pX, pDpS, DyM, dtdy, qn);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a.Qn[k * plane + cidx] = fluid ? qn[k] : sq[s_lo][k][lane];
-            const long long term = __double2ll_rn(detector_term(K, qn) * C.fix_scale);
+            for (int k = 0; k < 4; ++k) Qnp[k * plane + cidx] = fluid ? qn[k] : sq[s_lo][k][lane];
+            const long long term = __double2ll_rn(detector_term(K, qn) * M.fix_scale);
             const double rate = cfl_rate(K, qn);
             colfix += fluid ? term : 0ll;
             lam = fluid ? fmax(lam, rate) : lam;
@@ -381,14 +374,28 @@ __device__ void march(const StepArgs &a, unsigned long long ka, unsigned long lo
         }
         nF = fc_mid;
     }
-    const Control &C = control_at(ca);
-    if (out_lane && colfix != 0) atomicAdd((unsigned long long *)&C.S_out[i], (unsigned long long)colfix);
+    {
+        const Member &M = member_at(ma, b);
+        const int m_next = a.m3 == 2 ? 0 : a.m3 + 1;
+        if (out_lane && colfix != 0) atomicAdd((unsigned long long *)&M.S[m_next][i], (unsigned long long)colfix);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lam = fmax(lam, __shfl_xor(lam, off, 64));
+            bad |= __shfl_xor(bad, off, 64);
+        }
+        if (lane == 0) {
+            if (lam > 0.0) atomicMax(M.lam[m_next], (unsigned long long)__double_as_longlong(lam));
+            if (bad) atomicOr(M.flag, 1);
+        }
+    }
 
     // recorded cost of the rows marched here, for the next step's partition
+    const Control &C = control_at(ca);
+    const long long cbase = member_at(ma, b).cost0 + (long long)strip * ny;
     const double spent = (double)(clock64() - t_begin);
     const float per_row = (float)(spent / (E - j0));
-    for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[(size_t)strip * C.ny + rr] = per_row;
-    if (lane == 0) atomicAdd(&C.Ts_out[strip], spent);
+    for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[cbase + rr] = per_row;
+    if (lane == 0) atomicAdd(&C.Ts_out[g], spent);
 }
 
 // A split costs the thief a halo (two extra reconstructed rows and a row of loads), so only ranges
@@ -475,43 +482,46 @@ __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E,
     return false;
 }
 
-__global__ __launch_bounds__(64) void step_kernel(StepArgs a)
+// Member and local strip of global strip g.
+__device__ __forceinline__ void strip_owner(unsigned long long ma, unsigned long long ca, int g, int *b, int *s)
+{
+    g = __builtin_amdgcn_readfirstlane(g);
+    *b = __builtin_amdgcn_readfirstlane(control_at(ca).strip_member[g]);
+    *s = g - member_at(ma, *b).strip0;
+}
+
+__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
 {
     __shared__ double sq[3][4][64];
     __shared__ int sf[3][64];
 
     const int lane = threadIdx.x, w = blockIdx.x;
-    const unsigned long long ka = a.kaddr, ca = a.caddr;
-    double dt, dtdx, dtdy;
+    const unsigned long long ma = a.maddr, ca = a.caddr;
+    int nm, P;
     {
-        const Consts &K = consts_at(ka);
         const Control &C = control_at(ca);
-        if (a.cfl_dt) {
-            const double lmax = __longlong_as_double((long long)*C.lam_in);
-            dt = (lmax > 0.0 && isfinite(lmax)) ? K.cfl / lmax : 0.0;
-        } else {
-            dt = a.dt_arg;
-        }
-        if (w == 0 && lane == 0) {
-            *C.t += dt;
-            *C.lam_clear = 0ull;
-            if (!(dt > 0.0)) atomicOr(C.flag, 2);
-        }
-        dtdx = dt * K.inv_dx;
-        dtdy = dt * K.inv_dy;
-
-        // the next step's range list and accumulators (this step does not touch them otherwise)
-        for (int s = w * 64 + lane; s < C.max_slots; s += C.P * 64) C.desc_next[s] = 0ull;
-        for (int c = w * 64 + lane; c < a.nx; c += C.P * 64) C.S_clear[c] = 0;
-        for (int c = w * 64 + lane; c < C.nstrips; c += C.P * 64) C.Ts_clear[c] = 0.0;
+        nm = C.nmembers;
+        P = C.P;
+        // the next step's range list and strip totals (this step does not touch them otherwise)
+        for (int s = w * 64 + lane; s < C.max_slots; s += P * 64) C.desc_next[s] = 0ull;
+        for (int c = w * 64 + lane; c < C.nstrips; c += P * 64) C.Ts_clear[c] = 0.0;
         if (w == 0 && lane == 0) *C.nranges_next = C.R0;
     }
-
-    double lam = 0.0;
-    int bad = 0;
+    // per member (wavefront b mod P): elapsed time, and the third rotation buffers cleared
+    const int m_clear = a.m3 == 0 ? 2 : a.m3 - 1;
+    for (int b = w; b < nm; b += P) {
+        const double dt = member_dt(a, ma, b);
+        const Member &M = member_at(ma, b);
+        for (int c = lane; c < M.K.nx; c += 64) M.S[m_clear][c] = 0;
+        if (lane == 0) {
+            *M.t += dt;
+            *M.lam[m_clear] = 0ull;
+            if (!(dt > 0.0)) atomicOr(M.flag, 2);
+        }
+    }
 
     // ---- this wavefront's range: the cost interval [w, w+1) T/P of the recorded costs ---------
-    int strip = 0, j0 = 0, E = 0, slot = w, head_strip = -1;
+    int g = 0, j0 = 0, E = 0, slot = w, head_g = -1;
     double head_off = 0.0;
     bool have = false;
     {
@@ -520,68 +530,80 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs a)
         for (int c = lane; c < C.nstrips; c += 64) total += C.Ts_in[c];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
-        const double step = total / C.P;
-        const double xs[2] = {w * step, w + 1 < C.P ? (w + 1) * step : total};
+        const double step = total / P;
+        // (the last share ends beyond every strip: its end is not compared against a total summed
+        // in another order)
+        const double xs[2] = {w * step, w + 1 < P ? (w + 1) * step : 1e300};
         int sidx[2];
         double soff[2];
         locate<2>(C.Ts_in, C.nstrips, xs, sidx, soff);
-        const int s_w = sidx[0], s_next = sidx[1];
-        if (s_w < C.nstrips) {
-            const double rt[2] = {soff[0], s_next == s_w ? soff[1] : 1e300};
+        const int g_w = sidx[0], g_next = sidx[1];
+        if (g_w < C.nstrips) {
+            int b, sl;
+            strip_owner(ma, ca, g_w, &b, &sl);
+            const Member &M = member_at(ma, b);
+            const int ny = M.K.ny;
+            const double rt[2] = {soff[0], g_next == g_w ? soff[1] : 1e300};
             int ridx[2];
             double roff[2];
-            locate<2>(C.cost_in + (size_t)s_w * C.ny, C.ny, rt, ridx, roff);
-            const int lo = ridx[0], hi = s_next == s_w ? ridx[1] : C.ny;
+            locate<2>(C.cost_in + M.cost0 + (long long)sl * ny, ny, rt, ridx, roff);
+            const int lo = ridx[0], hi = g_next == g_w ? ridx[1] : ny;
             // published with atomic stores: other wavefronts read and update them atomically
-            if (lane == 0 && lo < hi) atomicExch(C.desc + w, d_make(true, s_w, hi, min(lo + a.B, hi)));
+            if (lane == 0 && lo < hi) atomicExch(C.desc + w, d_make(true, g_w, hi, min(lo + a.B, hi)));
             if (lo < hi) {
                 have = true;
-                strip = s_w;
+                g = g_w;
                 j0 = lo;
                 E = min(lo + a.B, hi);
             }
-            // strips the share spans whole are left unowned (rare: a strip cheaper than a share)
-            for (int s = s_w + 1 + lane; s < s_next && s < C.nstrips; s += 64)
-                atomicExch(C.desc + C.P + s, d_make(false, s, C.ny, 0));
+            // strips the share spans whole are left unowned (a strip cheaper than a share)
+            // (lanes hold strips of different members: the member's height is a per-lane load)
+            for (int s = g_w + 1 + lane; s < g_next && s < C.nstrips; s += 64) {
+                const int ny_s = ((const Member *)ma)[C.strip_member[s]].K.ny;
+                atomicExch(C.desc + P + s, d_make(false, s, ny_s, 0));
+            }
             // the head of the strip the share ends in is this wavefront's too: published owned and
             // unclaimed once its extent is known (after the first range is marched)
-            if (s_next > s_w && s_next < C.nstrips) {
-                head_strip = s_next;
+            if (g_next > g_w && g_next < C.nstrips) {
+                head_g = g_next;
                 head_off = soff[1];
             }
         }
     }
-    if (have) march(a, ka, ca, sq, sf, strip, j0, E, slot, dt, dtdx, dtdy, lam, bad);
-    if (head_strip >= 0) {
-        const Control &C = control_at(ca);
-        const double ht[1] = {head_off};
-        int hidx[1];
-        double hoff[1];
-        locate<1>(C.cost_in + (size_t)head_strip * C.ny, C.ny, ht, hidx, hoff);
-        const int hend = hidx[0];
-        if (hend > 0) {
-            // nobody else can know this range yet: it is claimed directly and then published
-            const int e0 = min(a.B, hend);
-            if (lane == 0) atomicExch(C.desc + C.P + head_strip, d_make(true, head_strip, hend, e0));
-            march(a, ka, ca, sq, sf, head_strip, 0, e0, C.P + head_strip, dt, dtdx, dtdy, lam, bad);
-        }
-    }
-    have = steal(ca, a.B, &strip, &j0, &E, &slot);
-    while (have) {
-        march(a, ka, ca, sq, sf, strip, j0, E, slot, dt, dtdx, dtdy, lam, bad);
-        have = steal(ca, a.B, &strip, &j0, &E, &slot);
-    }
 
-    // ---- CFL maximum and non-physical flag ------------------------------------------------------
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        lam = fmax(lam, __shfl_xor(lam, off, 64));
-        bad |= __shfl_xor(bad, off, 64);
-    }
-    if (lane == 0) {
-        const Control &C = control_at(ca);
-        if (lam > 0.0) atomicMax(C.lam_out, (unsigned long long)__double_as_longlong(lam));
-        if (bad) atomicOr(C.flag, 1);
+    // own range, then the owned head of the next strip, then whatever can be taken (one call site
+    // of the march, so that its code exists once)
+    for (int phase = 0;; ++phase) {
+        if (phase == 1) {
+            have = false;
+            if (head_g >= 0) {
+                const Control &C = control_at(ca);
+                int b, sl;
+                strip_owner(ma, ca, head_g, &b, &sl);
+                const int ny = member_at(ma, b).K.ny;
+                const double ht[1] = {head_off};
+                int hidx[1];
+                double hoff[1];
+                locate<1>(C.cost_in + member_at(ma, b).cost0 + (long long)sl * ny, ny, ht, hidx, hoff);
+                if (hidx[0] > 0) {
+                    // nobody else can know this range yet: it is claimed directly, then published
+                    g = head_g;
+                    j0 = 0;
+                    E = min(a.B, hidx[0]);
+                    slot = P + head_g;
+                    if (lane == 0) atomicExch(C.desc + slot, d_make(true, g, hidx[0], E));
+                    have = true;
+                }
+            }
+        } else if (phase >= 2) {
+            have = steal(ca, a.B, &g, &j0, &E, &slot);
+            if (!have) break;
+        }
+        if (have) {
+            int b, sl;
+            strip_owner(ma, ca, g, &b, &sl);
+            march(a, ma, ca, sq, sf, b, g, sl, j0, E, slot);
+        }
     }
 }
 
@@ -635,13 +657,14 @@ __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, in
 // Schedule state of the next step after bn_set_state or a change of the launch shape: empty
 // descriptor list, uniform recorded costs (1 per row), cleared strip totals to accumulate into.
 __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
-                                     double *Ts_in, double *Ts_acc, int nstrips, int ny)
+                                     long long nrows, double *Ts_in, double *Ts_acc, const int *strip_member,
+                                     const Member *members, int nstrips)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < max_slots) desc[s] = 0ull;
-    if (s < (long long)nstrips * ny) cost[s] = 1.0f;
+    if (s < nrows) cost[s] = 1.0f;
     if (s < nstrips) {
-        Ts_in[s] = (double)ny;
+        Ts_in[s] = (double)members[strip_member[s]].K.ny;
         Ts_acc[s] = 0.0;
     }
     if (s == 0) *nranges = R0;

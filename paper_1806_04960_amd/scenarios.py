@@ -221,15 +221,17 @@ def equilibrium_box(obstacle: bool, nx: int = 100, ny: int = 100) -> Scenario:
     return _fill(s, np.ones((ny, nx), bool))
 
 
-def ensemble(seed: int = 0, count: int = 64):
+ENSEMBLE_SIZES = ((256, 128), (512, 256), (768, 384), (1024, 512))
+
+
+def ensemble(seed: int = 0, count: int = 64, sizes=ENSEMBLE_SIZES):
     """Batch of uneven dam breaks on a 4 m x 2 m tank: sizes drawn from {256x128, 512x256,
-    768x384, 1024x512}; H ~ U[0.3, 1.0], W ~ U[0.3, 1.2]; 0-2 obstacles 0.1 m wide at
-    x ~ U[W + 0.2, 3.8] with heights U[0.05, 0.3]; k0 = 6.54e5; 500 steps each."""
+    768x384, 1024x512} (or the given list); H ~ U[0.3, 1.0], W ~ U[0.3, 1.2]; 0-2 obstacles
+    0.1 m wide at x ~ U[W + 0.2, 3.8] with heights U[0.05, 0.3]; k0 = 6.54e5; 500 steps each."""
     rng = np.random.default_rng(seed)
-    sizes = [(256, 128), (512, 256), (768, 384), (1024, 512)]
     out = []
     for k in range(count):
-        nx, ny = sizes[int(rng.integers(0, 4))]
+        nx, ny = sizes[int(rng.integers(0, len(sizes)))]
         H, W = rng.uniform(0.3, 1.0), rng.uniform(0.3, 1.2)
         n_obs = int(rng.integers(0, 3))
         s = Scenario(f"ensemble_{k}", nx, ny, 0.0, 4.0, 0.0, 2.0, k0=6.54e5, steps=500,

@@ -77,3 +77,54 @@ def test_null_arguments():
     assert L.bn_set_launch(None, 0, 0) == bn2d.BN_EINVAL
     assert L.bn_get_launch(None, None, None) == bn2d.BN_EINVAL
     L.bn_destroy(None)
+
+
+def _batch_create(scens, solids=None):
+    L = bn2d.lib()
+    n = len(scens)
+    grids = (bn2d.Grid * n)(*[bn2d.grid_of(s) for s in scens])
+    params = (bn2d.Params * n)(*[bn2d.params_of(s) for s in scens])
+    sp = None
+    keep = []
+    if solids is not None:
+        sp = (ctypes.POINTER(ctypes.c_uint8) * n)()
+        for k, m in enumerate(solids):
+            if m is not None:
+                m = np.ascontiguousarray(m, dtype=np.uint8)
+                keep.append(m)
+                sp[k] = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    out = ctypes.c_void_p()
+    return L.bn_batch_create(n, grids, params, sp, None, ctypes.byref(out)), out
+
+
+def test_batch_create_rejects_any_bad_member():
+    good = sc.uniform_tank(4, 4)
+    bad = sc.uniform_tank(4, 4)
+    bad.cfl = 2.0
+    rc, b = _batch_create([good, bad, good])
+    assert rc == bn2d.BN_EINVAL and not b.value
+    solid = np.zeros((4, 4), np.uint8)
+    solid[3, 0] = 1  # solid above fluid in column 0
+    rc, b = _batch_create([good, good], [None, solid])
+    assert rc == bn2d.BN_EUNSUPPORTED and not b.value
+
+
+def test_batch_null_arguments_and_bad_counts():
+    L = bn2d.lib()
+    out = ctypes.c_void_p()
+    g = (bn2d.Grid * 1)(bn2d.grid_of(sc.uniform_tank(4, 4)))
+    p = (bn2d.Params * 1)(bn2d.params_of(sc.uniform_tank(4, 4)))
+    assert L.bn_batch_create(0, g, p, None, None, ctypes.byref(out)) == bn2d.BN_EINVAL
+    assert L.bn_batch_create(-1, g, p, None, None, ctypes.byref(out)) == bn2d.BN_EINVAL
+    assert L.bn_batch_create(1, None, p, None, None, ctypes.byref(out)) == bn2d.BN_EINVAL
+    assert L.bn_batch_create(1, g, None, None, None, ctypes.byref(out)) == bn2d.BN_EINVAL
+    assert L.bn_batch_create(1, g, p, None, None, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_set_state(None, 0, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_get_state(None, 0, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_run(None, 1) == bn2d.BN_EINVAL
+    assert L.bn_batch_get_time(None, 0, None, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_get_y0(None, 0, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_status(None, None) == bn2d.BN_EINVAL
+    assert L.bn_batch_set_launch(None, 0, 0) == bn2d.BN_EINVAL
+    assert L.bn_batch_get_launch(None, None, None) == bn2d.BN_EINVAL
+    L.bn_batch_destroy(None)
