@@ -100,7 +100,7 @@ int bn_get_y0(bn_ctx *ctx, double *y0_host);
 int bn_status(bn_ctx *ctx);
 
 /* Launch shape of the step kernel.  Wavefronts march strips of 60 columns and claim rows in blocks
- * of rows_per_block (1..4096, 0 = default 32); the launch is persistent with `wavefronts`
+ * of rows_per_block (1..4096, 0 = default 4); the launch is persistent with `wavefronts`
  * wavefronts (1..65536, 0 = default: as many as the device holds at once).  Results are bitwise the same
  * for every shape: each cell is computed by the same arithmetic whatever wavefront does it, and
  * the free-surface integral is summed exactly (64-bit fixed point).  Synchronises the stream. */

@@ -19,8 +19,8 @@ __global__ void reduce_kernel(const double *Q, const uint8_t *solid, long long *
                               unsigned long long *lam_slot, int *flag, Consts K, int H);
 __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K);
 __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
-                                     long long nrows, double *Ts_in, double *Ts_acc, const int *strip_member,
-                                     const Member *members, int nstrips);
+                                     long long nrows, double *Ts_in, double *Ts_acc, const bn::StripInfo *strips,
+                                     int nstrips);
 __global__ void zero_kernel(long long *p, int n);
 __global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, double *y0, Consts K);
 }  // namespace bn
@@ -28,7 +28,7 @@ __global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, dou
 namespace {
 
 constexpr int kOutCols = 60;  // output columns per wavefront (64 lanes minus a 2-column halo each side)
-constexpr int kDefaultRowsPerBlock = 32;
+constexpr int kDefaultRowsPerBlock = 4;
 
 thread_local std::string g_last_hip_error;
 
@@ -157,7 +157,7 @@ struct bn_batch {
     int *nranges = nullptr;              // [2]
     float *cost = nullptr;               // [2][nrows]
     double *Ts = nullptr;                // [3][nstrips]
-    int *strip_member = nullptr;         // [nstrips]
+    bn::StripInfo *strips = nullptr;     // [nstrips]
     int *flag = nullptr;                 // scheduler error (4)
 };
 
@@ -175,7 +175,7 @@ void free_batch(bn_batch *b)
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
-    void *ptrs[] = {b->members, b->ctl, b->desc, b->nranges, b->cost, b->Ts, b->strip_member, b->flag};
+    void *ptrs[] = {b->members, b->ctl, b->desc, b->nranges, b->cost, b->Ts, b->strips, b->flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete b;
@@ -227,7 +227,7 @@ int write_tables(bn_batch *b)
             C.Ts_in = b->Ts + mm * ns;
             C.Ts_out = b->Ts + ((mm + 1) % 3) * ns;
             C.Ts_clear = b->Ts + ((mm + 2) % 3) * ns;
-            C.strip_member = b->strip_member;
+            C.strips = b->strips;
             C.flag = b->flag;
             C.nstrips = b->nstrips;
             C.nmembers = (int)b->g.size();
@@ -248,7 +248,7 @@ int init_schedule(bn_batch *b)
     hipLaunchKernelGGL(bn::init_schedule_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream,
                        b->desc + (size_t)b->par * b->max_slots, b->nranges + b->par, b->R0, b->max_slots,
                        b->cost + (size_t)b->par * b->nrows, b->nrows, b->Ts + (size_t)b->m3 * ns,
-                       b->Ts + (size_t)((b->m3 + 1) % 3) * ns, b->strip_member, b->members, b->nstrips);
+                       b->Ts + (size_t)((b->m3 + 1) % 3) * ns, b->strips, b->nstrips);
     HIP_TRY(hipGetLastError());
     return BN_OK;
 }
@@ -342,7 +342,7 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
         g_last_hip_error = std::string("hipMalloc: ") + hipGetErrorString(e);      \
         return fail(BN_ENOMEM);                                                    \
     }
-    std::vector<int> strip_member;
+    std::vector<bn::StripInfo> strips;
     for (int k = 0; k < count; ++k) {
         Grid &g = b->g[k];
         g.grid = grids[k];
@@ -396,7 +396,7 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
         M.cost0 = b->nrows;
         b->nstrips += M.nstrips;
         b->nrows += (long long)M.nstrips * ny;
-        for (int s = 0; s < M.nstrips; ++s) strip_member.push_back(k);
+        for (int s = 0; s < M.nstrips; ++s) strips.push_back({k, s, ny, 0, M.cost0 + (long long)s * ny});
     }
     if (b->nstrips > 0x7FFF) return fail(BN_EINVAL);
     ALLOC(b->members, sizeof(bn::Member) * count);
@@ -404,10 +404,10 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
     ALLOC(b->nranges, sizeof(int) * 2);
     ALLOC(b->cost, sizeof(float) * 2 * (size_t)b->nrows);
     ALLOC(b->Ts, sizeof(double) * 3 * (size_t)b->nstrips);
-    ALLOC(b->strip_member, sizeof(int) * (size_t)b->nstrips);
+    ALLOC(b->strips, sizeof(bn::StripInfo) * (size_t)b->nstrips);
     ALLOC(b->flag, sizeof(int));
 #undef ALLOC
-    e = hipMemcpy(b->strip_member, strip_member.data(), sizeof(int) * strip_member.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(b->strips, strips.data(), sizeof(bn::StripInfo) * strips.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->nranges, 0, sizeof(int) * 2);
     if (e == hipSuccess) e = hipMemset(b->flag, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(b->Ts, 0, sizeof(double) * 3 * (size_t)b->nstrips);

@@ -23,6 +23,16 @@ struct Member {
     long long cost0;                // offset of its first row in the cost arrays
 };
 
+// One column strip of the batch: its grid, its index within that grid, the grid's height and the
+// offset of its first row in the per-row cost arrays.
+struct StripInfo {
+    int member;
+    int local;
+    int ny;
+    int pad;
+    long long cost_base;
+};
+
 // Scheduling state of the whole batch for one combination of the rotations (range lists and
 // row costs: slot p mod 2; strip cost totals: m mod 3).
 struct Control {
@@ -35,7 +45,7 @@ struct Control {
     const double *Ts_in;            // recorded cost per global strip (previous step)
     double *Ts_out;                 // ... accumulated by this step
     double *Ts_clear;               // third buffer, zeroed for the next step
-    const int *strip_member;        // member of each global strip
+    const StripInfo *strips;        // every global strip
     int *flag;                      // batch-wide scheduler error (4)
     int nstrips;                    // global strips
     int nmembers;

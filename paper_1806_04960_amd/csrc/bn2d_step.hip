@@ -95,67 +95,104 @@ __device__ __forceinline__ double wave_incl_scan(double v)
     return v;
 }
 
-// For each target t[k]: the index i of v[0..n) with v[0] + ... + v[i-1] <= t[k] < v[0] + ... + v[i]
-// (n if there is none) and t[k] minus the lower bound.  Lane l sums the contiguous entries
-// [l m, (l+1) m), m = ceil(n / 64); one wave scan over the lane sums finds the lane holding the
-// target, which then walks its entries.  Every wavefront computing the same target on the same
-// data gets the same answer (the summation order is fixed).
-template <int NT, class T>
-__device__ void locate(const T *v, int n, const double (&t)[NT], int (&idx)[NT], double (&off)[NT])
-{
-    const int lane = threadIdx.x;
-    const int m = (n + 63) / 64, b = min(lane * m, n), e = min(b + m, n);
-    // loads 16 at a time from clamped addresses (no branch, one wait per batch)
-    auto batch = [&](int c, double (&vv)[16]) {
+// Prefix sums of v[0..n) spread over the wavefront: lane l holds the contiguous entries
+// [l m, (l+1) m), m = ceil(n / 64), their sum, and (one wave scan) the sums before and through
+// them.  find(t) returns the index i with v[0] + ... + v[i-1] <= t < v[0] + ... + v[i] (n if there
+// is none) and t minus that lower bound.  Every wavefront computing the same target on the same
+// data gets the same answer (the summation order is fixed).  Up to kHeld entries per lane are kept
+// in registers, so that finding needs no further loads; longer lists are walked again from memory.
+template <class T>
+struct Chunks {
+    static constexpr int kHeld = 16;
+    const T *v;
+    int n, m, b, e;
+    double vv[kHeld];
+    double excl, incl, total;
+
+    __device__ void load(const T *v_, int n_)
+    {
+        const int lane = threadIdx.x;
+        v = v_;
+        n = n_;
+        m = (n + 63) / 64;
+        b = min(lane * m, n);
+        e = min(b + m, n);
+        double sum = 0.0;
+        // loads 16 at a time from clamped addresses (no branch, one wait per batch)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const double x = (double)v[min(c + u, n - 1)];
-            vv[u] = c + u < e ? x : 0.0;
+        for (int u = 0; u < kHeld; ++u) {
+            const double x = (double)v[min(b + u, n - 1)];
+            vv[u] = b + u < e ? x : 0.0;
         }
-    };
-    double sum = 0.0;
-    for (int c = b; c < e; c += 16) {
-        double vv[16];
-        batch(c, vv);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) sum += vv[u];
-    }
-    const double incl = wave_incl_scan(sum), excl = incl - sum;
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        idx[k] = n;
-        off[k] = 0.0;
-        const unsigned long long mask = __ballot(b < e && excl <= t[k] && t[k] < incl);
-        if (!mask) continue;
-        const int l = __ffsll((long long)mask) - 1;
-        // lane l walks its entries; the others follow along and discard
-        const int lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
-        const double lx = __shfl(excl, l, 64);
-        int found = le - 1;
-        double rem = 0.0, acc = lx;
-        bool done = false;
-        for (int c = lb; c < le && !done; c += 16) {
-            double vv[16];
+        for (int u = 0; u < kHeld; ++u) sum += vv[u];
+        for (int c = b + kHeld; c < e; c += 16) {
+            double w[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const double x = (double)v[min(c + u, n - 1)];
-                vv[u] = c + u < le ? x : 0.0;
+                w[u] = c + u < e ? x : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < 16; ++u) sum += w[u];
+        }
+        incl = wave_incl_scan(sum);
+        excl = incl - sum;
+        total = __shfl(incl, 63, 64);
+    }
+
+    __device__ void find(double t, int &idx, double &off) const
+    {
+        const int lane = threadIdx.x;
+        idx = n;
+        off = 0.0;
+        const unsigned long long mask = __ballot(b < e && excl <= t && t < incl);
+        if (!mask) return;
+        const int l = __ffsll((long long)mask) - 1;
+        int found;
+        double rem;
+        if (m <= kHeld) {
+            // every lane walks its own entries; lane l's answer is the one
+            found = e - 1;
+            rem = 0.0;
+            double acc = excl;
+            bool done = false;
+#pragma unroll
+            for (int u = 0; u < kHeld; ++u) {
                 const double next = acc + vv[u];
-                if (!done && c + u < le && t[k] < next) {
-                    found = c + u;
-                    rem = t[k] - acc;
+                if (!done && b + u < e && t < next) {
+                    found = b + u;
+                    rem = t - acc;
                     done = true;
                 }
                 acc = next;
             }
+            found = __shfl(found, l, 64);
+            rem = __shfl(rem, l, 64);
+        } else {
+            // the wavefront walks lane l's entries 64 at a time
+            const int lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
+            double acc = __shfl(excl, l, 64);
+            found = le - 1;
+            rem = 0.0;
+            for (int c = lb; c < le; c += 64) {
+                const bool in = c + lane < le;
+                const double x = in ? (double)v[c + lane] : 0.0;
+                const double si = wave_incl_scan(x);
+                const unsigned long long hit = __ballot(in && t < acc + si);
+                if (hit) {
+                    const int u = __ffsll((long long)hit) - 1;
+                    found = c + u;
+                    rem = t - (acc + __shfl(si - x, u, 64));
+                    break;
+                }
+                acc += __shfl(si, 63, 64);
+            }
         }
-        idx[k] = found;
-        off[k] = rem;
+        idx = found;
+        off = rem;
     }
-}
+};
 
 // Stencil accessor over the LDS ring: rows s[0..2] (below, centre, above), lane offsets -1..1.
 struct LdsStencil {
@@ -391,7 +428,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
 
     // recorded cost of the rows marched here, for the next step's partition
     const Control &C = control_at(ca);
-    const long long cbase = member_at(ma, b).cost0 + (long long)strip * ny;
+    const long long cbase = member_at(ma, b).cost0 + (long long)strip * ny;  // (the strip's cost_base)
     const double spent = (double)(clock64() - t_begin);
     const float per_row = (float)(spent / (E - j0));
     for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[cbase + rr] = per_row;
@@ -400,7 +437,8 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
 
 // A split costs the thief a halo (two extra reconstructed rows and a row of loads), so only ranges
 // with at least this many unclaimed rows are split.
-constexpr int kMinSplit = 8;
+constexpr int kMinSplit = 3;
+constexpr int kScanBatch = 40;  // descriptors per lane loaded at once by a thief
 
 // Find work: a range nobody owns (taken whole) or a large range being marched with at least
 // kMinSplit unclaimed rows (upper half taken).  Returns false when there is none.  On success the
@@ -415,15 +453,17 @@ __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E,
         n = n < a.max_slots ? n : a.max_slots;
         // key = score << 40 | hash << 32 | (2^31 - 1 - slot): larger is better
         long long best = 0;
-        for (int base = 0; base < n; base += 64 * 8) {
-            unsigned long long wd[8];
+        // (all of a batch's loads are in flight together: one batch covers a launch's initial
+        // descriptors and its first splits)
+        for (int base = 0; base < n; base += 64 * kScanBatch) {
+            unsigned long long wd[kScanBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kScanBatch; ++u) {
                 const int s = base + u * 64 + lane;
                 wd[u] = s < n ? load_word(a.desc + s) : 0ull;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kScanBatch; ++u) {
                 const int s = base + u * 64 + lane;
                 const int rem = d_end(wd[u]) - d_cur(wd[u]);
                 // unowned ranges first, then by size class (floor log2 of the unclaimed rows);
@@ -482,12 +522,14 @@ __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E,
     return false;
 }
 
-// Member and local strip of global strip g.
-__device__ __forceinline__ void strip_owner(unsigned long long ma, unsigned long long ca, int g, int *b, int *s)
+// The record of global strip g (read through the scalar cache).
+typedef const __attribute__((address_space(4))) StripInfo *StripPtr;
+__device__ __forceinline__ StripInfo strip_at(unsigned long long ca, int g)
 {
-    g = __builtin_amdgcn_readfirstlane(g);
-    *b = __builtin_amdgcn_readfirstlane(control_at(ca).strip_member[g]);
-    *s = g - member_at(ma, *b).strip0;
+    unsigned long long addr = (unsigned long long)(uintptr_t)(control_at(ca).strips +
+                                                              __builtin_amdgcn_readfirstlane(g));
+    asm volatile("" : "+s"(addr));
+    return *(const StripInfo *)(StripPtr)addr;
 }
 
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
@@ -526,28 +568,23 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
     bool have = false;
     {
         const Control &C = control_at(ca);
-        double total = 0.0;
-        for (int c = lane; c < C.nstrips; c += 64) total += C.Ts_in[c];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
-        const double step = total / P;
-        // (the last share ends beyond every strip: its end is not compared against a total summed
-        // in another order)
-        const double xs[2] = {w * step, w + 1 < P ? (w + 1) * step : 1e300};
-        int sidx[2];
-        double soff[2];
-        locate<2>(C.Ts_in, C.nstrips, xs, sidx, soff);
-        const int g_w = sidx[0], g_next = sidx[1];
+        Chunks<double> strips;
+        strips.load(C.Ts_in, C.nstrips);
+        const double step = strips.total / P;
+        // (the last share ends beyond every strip: its end is not compared against the total)
+        int g_w, g_next;
+        double soff0, soff1;
+        strips.find(w * step, g_w, soff0);
+        strips.find(w + 1 < P ? (w + 1) * step : 1e300, g_next, soff1);
         if (g_w < C.nstrips) {
-            int b, sl;
-            strip_owner(ma, ca, g_w, &b, &sl);
-            const Member &M = member_at(ma, b);
-            const int ny = M.K.ny;
-            const double rt[2] = {soff[0], g_next == g_w ? soff[1] : 1e300};
-            int ridx[2];
-            double roff[2];
-            locate<2>(C.cost_in + M.cost0 + (long long)sl * ny, ny, rt, ridx, roff);
-            const int lo = ridx[0], hi = g_next == g_w ? ridx[1] : ny;
+            const StripInfo si = strip_at(ca, g_w);
+            Chunks<float> rows;
+            rows.load(C.cost_in + si.cost_base, si.ny);
+            int lo, hi;
+            double roff;
+            rows.find(soff0, lo, roff);
+            if (g_next == g_w) rows.find(soff1, hi, roff);
+            else hi = si.ny;
             // published with atomic stores: other wavefronts read and update them atomically
             if (lane == 0 && lo < hi) atomicExch(C.desc + w, d_make(true, g_w, hi, min(lo + a.B, hi)));
             if (lo < hi) {
@@ -557,16 +594,13 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
                 E = min(lo + a.B, hi);
             }
             // strips the share spans whole are left unowned (a strip cheaper than a share)
-            // (lanes hold strips of different members: the member's height is a per-lane load)
-            for (int s = g_w + 1 + lane; s < g_next && s < C.nstrips; s += 64) {
-                const int ny_s = ((const Member *)ma)[C.strip_member[s]].K.ny;
-                atomicExch(C.desc + P + s, d_make(false, s, ny_s, 0));
-            }
+            for (int s = g_w + 1 + lane; s < g_next && s < C.nstrips; s += 64)
+                atomicExch(C.desc + P + s, d_make(false, s, C.strips[s].ny, 0));
             // the head of the strip the share ends in is this wavefront's too: published owned and
             // unclaimed once its extent is known (after the first range is marched)
             if (g_next > g_w && g_next < C.nstrips) {
                 head_g = g_next;
-                head_off = soff[1];
+                head_off = soff1;
             }
         }
     }
@@ -578,20 +612,19 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
             have = false;
             if (head_g >= 0) {
                 const Control &C = control_at(ca);
-                int b, sl;
-                strip_owner(ma, ca, head_g, &b, &sl);
-                const int ny = member_at(ma, b).K.ny;
-                const double ht[1] = {head_off};
-                int hidx[1];
-                double hoff[1];
-                locate<1>(C.cost_in + member_at(ma, b).cost0 + (long long)sl * ny, ny, ht, hidx, hoff);
-                if (hidx[0] > 0) {
+                const StripInfo si = strip_at(ca, head_g);
+                Chunks<float> rows;
+                rows.load(C.cost_in + si.cost_base, si.ny);
+                int hend;
+                double hoff;
+                rows.find(head_off, hend, hoff);
+                if (hend > 0) {
                     // nobody else can know this range yet: it is claimed directly, then published
                     g = head_g;
                     j0 = 0;
-                    E = min(a.B, hidx[0]);
+                    E = min(a.B, hend);
                     slot = P + head_g;
-                    if (lane == 0) atomicExch(C.desc + slot, d_make(true, g, hidx[0], E));
+                    if (lane == 0) atomicExch(C.desc + slot, d_make(true, g, hend, E));
                     have = true;
                 }
             }
@@ -600,9 +633,8 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
             if (!have) break;
         }
         if (have) {
-            int b, sl;
-            strip_owner(ma, ca, g, &b, &sl);
-            march(a, ma, ca, sq, sf, b, g, sl, j0, E, slot);
+            const StripInfo si = strip_at(ca, g);
+            march(a, ma, ca, sq, sf, si.member, g, si.local, j0, E, slot);
         }
     }
 }
@@ -657,14 +689,14 @@ __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, in
 // Schedule state of the next step after bn_set_state or a change of the launch shape: empty
 // descriptor list, uniform recorded costs (1 per row), cleared strip totals to accumulate into.
 __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
-                                     long long nrows, double *Ts_in, double *Ts_acc, const int *strip_member,
-                                     const Member *members, int nstrips)
+                                     long long nrows, double *Ts_in, double *Ts_acc, const StripInfo *strips,
+                                     int nstrips)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < max_slots) desc[s] = 0ull;
     if (s < nrows) cost[s] = 1.0f;
     if (s < nstrips) {
-        Ts_in[s] = (double)members[strip_member[s]].K.ny;
+        Ts_in[s] = (double)strips[s].ny;
         Ts_acc[s] = 0.0;
     }
     if (s == 0) *nranges = R0;
