@@ -170,14 +170,156 @@ def ensemble_main(args):
     print(json.dumps(line), flush=True)
 
 
+def adjoint_main(args):
+    """Gradient of a wall-load functional through a trajectory of the 512 x 256 wall-impact
+    workload (seed 0): N steps of fixed dt (the CFL step of the initial state), loss
+    J = sum_n dt sum_j dy (alpha p)(Q^n) over the column in front of the wall, checkpoints every 20
+    steps, each segment recomputed and reversed with bn_adjoint_step.  Reports the cost of the whole
+    gradient (forward with checkpoints + recomputation + reverse) over a plain forward run, the
+    adjoint step's own throughput, and a check of the gradient along seeded directions of the
+    initial state against central differences of J."""
+    import numpy as np
+    import torch
+
+    from paper_1806_04960_amd import bn2d
+    from paper_1806_04960_amd import scenarios as sc
+
+    N, seg = args.steps, 20
+    s = sc.wall_impact(0)
+    iw = s.meta["wall_column"] - 1
+    n = s.nx * s.ny
+    print(f"# adjoint workload {s.nx}x{s.ny}, {N} steps, checkpoints every {seg}", file=sys.stderr, flush=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    sim = bn2d.Simulation(s)
+    q0 = torch.from_numpy(s.q).cuda()
+    sim.set_state(q0)
+    dt = sim.compute_dt()
+    w = torch.zeros((4, s.ny, s.nx), dtype=torch.float64, device="cuda")
+    fl = torch.from_numpy(s.fluid()).cuda()
+    w[0, :, iw] = dt * s.dy * s.k0 / s.rho0   # d(alpha p)/d(alpha rho) = k0/rho0
+    w[3, :, iw] = -dt * s.dy * s.k0           # d(alpha p)/d(alpha) = -k0
+    w *= fl
+
+    def loss(q_init):
+        sim.set_state(q_init)
+        J = torch.zeros((), dtype=torch.float64, device="cuda")
+        for _ in range(N):
+            sim.step(dt)
+            J += (w * sim.get_state()).sum()
+        return float(J)
+
+    def forward_plain():
+        sim.set_state(q0)
+        for _ in range(N):
+            sim.step(dt)
+
+    def gradient():
+        ck = [q0.clone()]
+        sim.set_state(q0)
+        for k in range(N):
+            sim.step(dt)
+            if (k + 1) % seg == 0 and k + 1 < N:
+                ck.append(sim.get_state())
+        lam = torch.zeros_like(q0)
+        buf = [None] * seg
+        for c in range(len(ck) - 1, -1, -1):
+            n0 = c * seg
+            m = min(seg, N - n0)
+            sim.set_state(ck[c])
+            buf[0] = ck[c]
+            for k in range(1, m):
+                sim.step(dt)
+                buf[k] = sim.get_state()
+            for k in range(m - 1, -1, -1):
+                lam = lam + w  # dJ/dQ^{n0+k+1}
+                lam = sim.adjoint_step(buf[k], lam, dt)
+        return lam
+
+    forward_plain()
+    gradient()
+    torch.cuda.synchronize()
+    reps = 3
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(reps):
+        forward_plain()
+    b.record()
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b) / reps
+    a.record()
+    for _ in range(reps):
+        g = gradient()
+    b.record()
+    torch.cuda.synchronize()
+    grad_ms = a.elapsed_time(b) / reps
+    # the adjoint step alone
+    lam = torch.randn((4, s.ny, s.nx), dtype=torch.float64, device="cuda")
+    out = torch.empty_like(lam)
+    a.record()
+    for _ in range(100):
+        sim.adjoint_step(q0, lam, dt, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    adj_ms = a.elapsed_time(b) / 100
+    a.record()
+    sim.set_state(q0)
+    for _ in range(100):
+        sim.step(dt)
+    b.record()
+    torch.cuda.synchronize()
+    step_ms = a.elapsed_time(b) / 100
+    print(f"# forward {fwd_ms:.2f} ms, gradient {grad_ms:.2f} ms (x{grad_ms / fwd_ms:.2f}); step {step_ms*1e3:.1f} us, "
+          f"adjoint step {adj_ms*1e3:.1f} us", file=sys.stderr, flush=True)
+
+    # gradient check along seeded patch directions (difference quotients at h and h/2)
+    rng = np.random.default_rng(0)
+    gn = g.cpu().numpy()
+    checks = []
+    scale = np.stack([np.abs(s.q[0])] * 3 + [np.abs(s.q[3])]) * s.fluid()
+    for m in range(args.fd_directions):
+        j0, i0 = int(rng.integers(0, s.ny // 2)), int(rng.integers(0, iw - 24))
+        d = np.zeros_like(s.q)
+        d[:, j0:j0 + 24, i0:i0 + 24] = rng.normal(size=(4, 24, 24))
+        d *= scale
+        dd = torch.from_numpy(d).cuda()
+        h = 1e-7
+        fd1 = (loss(q0 + h * dd) - loss(q0 - h * dd)) / (2 * h)
+        fd2 = (loss(q0 + h / 2 * dd) - loss(q0 - h / 2 * dd)) / h
+        ad = float(np.sum(gn * d))
+        checks.append({"patch": [j0, i0], "adjoint": ad, "fd": fd2, "rel": abs(ad - fd2) / abs(fd2),
+                       "fd_h_vs_h2": abs(fd1 - fd2) / abs(fd2)})
+        print(f"# direction {m}: {checks[-1]}", file=sys.stderr, flush=True)
+    sim.close()
+    line = {
+        "metric": "FP64 cell updates/sec",
+        "value": n / (adj_ms / 1e3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": N,
+        "warmup": 1,
+        "ms_per_step": adj_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"discrete adjoint, wall impact {s.nx}x{s.ny} seed 0, {N} steps of fixed dt, "
+                               f"checkpoints every {seg}", "nx": s.nx, "ny": s.ny},
+        "adjoint": {"forward_ms": fwd_ms, "gradient_ms": grad_ms, "cost_ratio": grad_ms / fwd_ms,
+                    "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3, "fd_checks": checks},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="dam_break",
-                    choices=["dam_break", "elliptic_drop", "dam_break_small", "ensemble"])
+                    choices=["dam_break", "elliptic_drop", "dam_break_small", "ensemble", "adjoint"])
     ap.add_argument("--members", type=int, default=64, help="ensemble size (workload ensemble)")
+    ap.add_argument("--fd-directions", type=int, default=4, help="gradient checks (workload adjoint)")
     ap.add_argument("--rows", type=int, default=None, help="rows per claimed block of the step kernel")
     ap.add_argument("--wavefronts", type=int, default=None, help="wavefronts of the persistent step kernel")
     ap.add_argument("--cpu-baseline-steps", type=int, default=4)
@@ -205,6 +347,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
         ensemble_main(args)
+        return
+    if args.workload == "adjoint":
+        adjoint_main(args)
         return
     s = build_workload(args.workload)
     print(f"# workload {s.name} {s.nx}x{s.ny}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,

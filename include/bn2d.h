@@ -112,6 +112,21 @@ int bn_get_launch(bn_ctx *ctx, int32_t *rows_per_block, int32_t *wavefronts);
 void bn_destroy(bn_ctx *ctx);
 const char *bn_strerror(int code);
 
+/* Discrete adjoint of one step with time step dt (the step of bn_step, Sec. 3 eq. Scheme with
+ * Sec. 3.1-3.5, differentiated in reverse mode with respect to the state at t^n):
+ *   lam_dev = (d Q^{n+1} / d Q^n)^T lam_next_dev,   Q^{n+1} = step(q_dev, dt).
+ * q_dev, lam_next_dev: caller-owned device buffers, 4 planes x nx*ny FP64 (the state layout);
+ * lam_dev receives the adjoint of the state at t^n in the same layout and must not overlap
+ * either input.  The context's own state, time and schedule are not touched; q_dev need not be
+ * the context's state.  dt is held fixed (the CFL maximum is not differentiated); the free-surface
+ * height is differentiated as the real column sum of Sec. 3.5; at the scheme's non-smooth points
+ * (limiter min/max, |u|, sign, the second-order and liquid switches, walls) the branch the step
+ * takes is differentiated.  The library allocates its scratch (about 75 doubles per cell) on the
+ * first call and keeps it until bn_destroy.  Asynchronous on the context's stream.  Errors:
+ * BN_EINVAL (null pointer, dt <= 0 or not finite), BN_ENOMEM, BN_EHIP.  A non-physical q_dev gives
+ * non-finite values. */
+int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev);
+
 /* ---- Batches: many grids advanced by one launch per step -------------------------------------
  * A batch holds `count` independent grids (members) of any sizes, parameters and masks, e.g. an
  * ensemble of scenarios too small to fill the device one by one.  Every bn_batch_run step advances

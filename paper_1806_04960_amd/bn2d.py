@@ -17,7 +17,7 @@ BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
            "bn_get_time", "bn_get_y0", "bn_status", "bn_set_launch", "bn_get_launch", "bn_destroy",
-           "bn_strerror", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
+           "bn_strerror", "bn_adjoint_step", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
            "bn_batch_get_time", "bn_batch_get_y0", "bn_batch_status", "bn_batch_set_launch",
            "bn_batch_get_launch", "bn_batch_destroy")
 
@@ -64,6 +64,7 @@ def lib():
         L.bn_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.bn_destroy.argtypes = [vp]
         L.bn_destroy.restype = None
+        L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp]
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
         i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
@@ -152,6 +153,20 @@ class Simulation:
 
     def run(self, n_steps: int):
         check(lib().bn_run(self._ctx, int(n_steps)), "bn_run")
+
+    def adjoint_step(self, q, lam_next, dt: float, out=None):
+        """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} for the step of length dt from state q
+        (``bn_adjoint_step``).  q, lam_next: contiguous float64 CUDA tensors [4, ny, nx]."""
+        import torch
+        shape = (4, self.ny, self.nx)
+        for name, t in (("q", q), ("lam_next", lam_next)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device="cuda")
+        check(lib().bn_adjoint_step(self._ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(lam_next.data_ptr()),
+                                    float(dt), ctypes.c_void_p(out.data_ptr())), "bn_adjoint_step")
+        return out
 
     def time(self):
         t, dt = ctypes.c_double(), ctypes.c_double()
@@ -285,3 +300,29 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def step_function():
+    """A ``torch.autograd.Function`` for one step of fixed length: ``StepFn.apply(sim, q, dt)``
+    returns the state after one step from q (through ``bn_set_state`` and ``bn_step``, so it
+    resets the context's state and time), and its backward is ``bn_adjoint_step``.  Long
+    trajectories are differentiated with checkpoints and recomputation by the caller."""
+    import torch
+
+    class StepFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sim, q, dt):
+            q = q.detach().contiguous()
+            sim.set_state(q)
+            sim.step(float(dt))
+            ctx.sim, ctx.dt = sim, float(dt)
+            ctx.save_for_backward(q)
+            return sim.get_state()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (q,) = ctx.saved_tensors
+            lam = ctx.sim.adjoint_step(q, grad_out.contiguous(), ctx.dt)
+            return None, lam, None
+
+    return StepFn

@@ -3,7 +3,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("bn2d_step.hip", "bn2d_api.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("bn2d_step.hip", "bn2d_adjoint.hip", "bn2d_api.hip")]
 LIB = os.path.join(HERE, "libbn2d.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

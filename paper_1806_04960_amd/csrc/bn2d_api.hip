@@ -25,6 +25,12 @@ __global__ void zero_kernel(long long *p, int n);
 __global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, double *y0, Consts K);
 }  // namespace bn
 
+// the discrete adjoint's passes (bn2d_adjoint.hip)
+int bn_adjoint_planes();
+hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
+                             const uint8_t *solid, const int *jb, const long long *S, double fix_inv, double dt,
+                             double *scratch, hipStream_t stream);
+
 namespace {
 
 constexpr int kOutCols = 60;  // output columns per wavefront (64 lanes minus a 2-column halo each side)
@@ -71,6 +77,8 @@ struct Grid {
     int *flag = nullptr;
     double *y0 = nullptr;               // [nx] staging for bn_get_y0
     double *dt = nullptr;               // staging for dt queries
+    double *adj = nullptr;              // adjoint scratch planes, allocated on first use
+    long long *adjS = nullptr;          // [nx] free-surface integral of the adjoint's state, + 2 words
     bool has_state = false;
 };
 
@@ -171,7 +179,7 @@ namespace {
 void free_batch(bn_batch *b)
 {
     for (Grid &g : b->g) {
-        void *ptrs[] = {g.q[0], g.q[1], g.solid, g.jb, g.S, g.lam, g.t, g.flag, g.y0, g.dt};
+        void *ptrs[] = {g.q[0], g.q[1], g.solid, g.jb, g.S, g.lam, g.t, g.flag, g.y0, g.dt, g.adj, g.adjS};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -615,6 +623,37 @@ int bn_get_launch(bn_ctx *c, int32_t *rows_per_block, int32_t *wavefronts)
 {
     if (!c) return BN_EINVAL;
     return bn_batch_get_launch(c->b, rows_per_block, wavefronts);
+}
+
+int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev)
+{
+    if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
+    bn_batch *b = c->b;
+    Grid &g = b->g[0];
+    const int nx = g.grid.nx, ny = g.grid.ny;
+    const size_t n = (size_t)nx * ny;
+    if (!g.adj) {
+        hipError_t e = hipMalloc(&g.adj, sizeof(double) * ((size_t)bn_adjoint_planes() * n + nx));
+        if (e == hipSuccess) e = hipMalloc(&g.adjS, sizeof(long long) * (nx + 2));
+        if (e != hipSuccess) {
+            if (g.adj) (void)hipFree(g.adj);
+            g.adj = nullptr;
+            g.adjS = nullptr;
+            g_last_hip_error = std::string("hipMalloc(adjoint scratch): ") + hipGetErrorString(e);
+            return BN_ENOMEM;
+        }
+    }
+    // the free-surface integral of the given state, exactly as a step from it would use it
+    long long *S = g.adjS;
+    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 2 + 255) / 256), dim3(256), 0, b->stream, S, nx + 2);
+    HIP_TRY(hipGetLastError());
+    const int H = 64;
+    hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
+                       g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, S, g.dev.fix_inv, dt, g.adj,
+                              b->stream));
+    return BN_OK;
 }
 
 void bn_destroy(bn_ctx *c)

@@ -245,6 +245,48 @@ def ensemble(seed: int = 0, count: int = 64, sizes=ENSEMBLE_SIZES):
     return out
 
 
+def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64):
+    """Reservoir released against a wall, the adjoint workload: [0,4] x [0,2], free-surface profile
+    h(x) piecewise linear through theta_k = 0.6 + 0.1 U(-1, 1) at x_k = 3.5 k / (n_theta - 1);
+    alpha is the liquid volume fraction of each cell below h(x_i) (two-level away from the surface,
+    fractional in the cell the surface cuts); a one-cell solid wall of height 0.4 in the first
+    column right of x = 3.5; dry (gas) right of it.  Hydrostatic density below each column's
+    free surface (the detector's value), k0 = 6.54e5, at rest.  The profile values are kept in
+    meta["theta"]."""
+    rng = np.random.default_rng(seed)
+    theta = 0.6 + 0.1 * rng.uniform(-1.0, 1.0, n_theta)
+    s = Scenario("wall_impact", nx, ny, 0.0, 4.0, 0.0, 2.0, k0=6.54e5, steps=400,
+                 meta={"seed": seed, "theta": theta.tolist()})
+    xc = s.xc()
+    iw = int(np.nonzero(xc > 3.5)[0][0])
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[s.yc() < 0.4, iw] = 1
+    s.solid = solid
+    s.meta["wall_column"] = iw
+    hx = np.interp(xc, 3.5 * np.arange(n_theta) / (n_theta - 1), theta)
+    hx[xc >= 3.5] = 0.0
+    ybot = s.y0 + np.arange(ny) * s.dy
+    frac = np.clip((hx[None, :] - ybot[:, None]) / s.dy, 0.0, 1.0)
+    frac[solid == 1] = 0.0
+    alpha = s.alpha_gas + frac * (s.alpha_liq - s.alpha_gas)
+    a = s.g * s.rho0 / s.k0
+    yc = s.yc()
+    rho = np.full((ny, nx), s.rho0)
+    for i in range(nx):
+        col_f = solid[:, i] == 0
+        jb = int(np.argmax(col_f)) if col_f.any() else ny
+        y_surf = (s.y0 + jb * s.dy) + s.dy * float(frac[:, i].sum())
+        liq = col_f & (yc < y_surf)
+        rho[liq, i] = s.rho0 * np.exp(-a * (yc[liq] - y_surf))
+    q = np.zeros((4, ny, nx))
+    q[0] = alpha * rho
+    q[3] = alpha
+    gas = np.array([s.alpha_gas * s.rho0, 0.0, 0.0, s.alpha_gas])
+    q[:, solid == 1] = gas[:, None]
+    s.q = q
+    return s
+
+
 # ---------------------------------------------------------------------------------------------
 # Small cases for the oracle's pins and the parity tests
 # ---------------------------------------------------------------------------------------------
@@ -287,6 +329,29 @@ def random_state(s: Scenario, seed: int, amp: float = 0.05, vel: float = 3.0) ->
     out = s.copy()
     out.q = q
     out.name = s.name + f"_noise{seed}"
+    return out
+
+
+def generic_state(s: Scenario, seed: int, rel: float = 1e-3, vel: float = 0.05) -> Scenario:
+    """A state near s.q with no two cells alike (for derivative checks, which need the scheme to be
+    differentiable: equal neighbours sit on the limiter's min/max ties, velocities near zero on the
+    kinks of |u| and sign(v)): every fluid cell's alpha rho scaled by 1 + rel U(-1, 1), alpha by
+    1 - rel U(0, 1), and u, v shifted by vel (1 + U(0, 1)), a drift away from zero."""
+    rng = np.random.default_rng(seed)
+    q = s.q.copy()
+    fl = s.fluid()
+    shape = (s.ny, s.nx)
+    u = np.where(q[0] != 0, q[1] / q[0], 0.0) + vel * (1.0 + rng.uniform(0, 1, shape))
+    v = np.where(q[0] != 0, q[2] / q[0], 0.0) + vel * (1.0 + rng.uniform(0, 1, shape))
+    ar = q[0] * (1.0 + rel * rng.uniform(-1, 1, shape))
+    al = q[3] * (1.0 - rel * rng.uniform(0, 1, shape))
+    q[0] = np.where(fl, ar, q[0])
+    q[1] = np.where(fl, ar * u, q[1])
+    q[2] = np.where(fl, ar * v, q[2])
+    q[3] = np.where(fl, al, q[3])
+    out = s.copy()
+    out.q = q
+    out.name = s.name + f"_generic{seed}"
     return out
 
 

@@ -1,0 +1,56 @@
+"""The adjoint oracle (the transpose of the oracle step's Jacobian by central differences) against
+what the scheme fixes independently of any derivative code:
+
+- conservation of alpha rho in a closed box (Sec. 3: every edge's D- and D+ of the first component
+  sum to the flux jump, and walls mirror): sum_c (alpha rho)^{n+1}_c = sum_c (alpha rho)^n_c for
+  every state, so the adjoint of lambda^{n+1} = (1, 0, 0, 0) everywhere is (1, 0, 0, 0) everywhere;
+- solid cells keep their state and are never read (Sec. 5): their adjoint passes through;
+- the stencil (Sec. 3.4, 3.1-3.3): an output cell depends on the states within two cells along x
+  and y and one diagonally, plus the alpha of the columns whose free surface its edges use
+  (its own and the two beside it, Sec. 3.5); every other entry of the adjoint is exactly zero.
+"""
+import numpy as np
+
+from paper_1806_04960_amd import scenarios as sc
+
+
+def _dt(oracle, s):
+    return 0.9 * oracle.cfl(s, s.q)[1]
+
+
+def test_mass_identity(oracle):
+    s = sc.generic_state(sc.dam_break_small(7, 6), seed=1)
+    lam = np.zeros_like(s.q)
+    lam[0] = 1.0
+    out = oracle.adjoint_fd(s, s.q, lam, _dt(oracle, s))
+    np.testing.assert_allclose(out[0], 1.0, atol=1e-7)
+    np.testing.assert_allclose(out[1:], 0.0, atol=1e-7)
+
+
+def test_solid_cells_pass_through(oracle):
+    s = sc.generic_state(sc.rest_with_obstacle(10, 6), seed=2)
+    rng = np.random.default_rng(5)
+    lam = rng.normal(size=s.q.shape)
+    out = oracle.adjoint_fd(s, s.q, lam, _dt(oracle, s))
+    solid = s.solid == 1
+    assert solid.any()
+    np.testing.assert_allclose(out[:, solid], lam[:, solid], rtol=0, atol=1e-8)
+
+
+def test_stencil_support(oracle):
+    # a second-order cell (its 3 x 3 stencil is liquid) with gas two rows above it
+    s = sc.generic_state(sc.rest_flat(11, 10), seed=3)
+    i, j = 5, 3
+    lam = np.zeros_like(s.q)
+    lam[:, j, i] = [1.0, 0.3, -0.7, 2.0]
+    out = oracle.adjoint_fd(s, s.q, lam, _dt(oracle, s))
+    J, I = np.meshgrid(np.arange(s.ny), np.arange(s.nx), indexing="ij")
+    di, dj = np.abs(I - i), np.abs(J - j)
+    support = ((di + dj) <= 2) | ((di <= 1) & (dj <= 1))
+    for k in range(3):
+        assert np.all(out[k][~support] == 0.0), k
+    assert np.all(out[3][~(support | (di <= 1))] == 0.0)
+    # something flows to every cell of the 3 x 3 stencil, and through the free surface to the
+    # alpha of the column's top cell
+    assert np.all(np.abs(out[0][(di <= 1) & (dj <= 1)]) > 0)
+    assert abs(out[3][s.ny - 1, i]) > 0
