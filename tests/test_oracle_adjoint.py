@@ -23,8 +23,9 @@ def test_mass_identity(oracle):
     lam = np.zeros_like(s.q)
     lam[0] = 1.0
     out = oracle.adjoint_fd(s, s.q, lam, _dt(oracle, s))
-    np.testing.assert_allclose(out[0], 1.0, atol=1e-7)
-    np.testing.assert_allclose(out[1:], 0.0, atol=1e-7)
+    # (the difference quotients' rounding: about 1e-13 per changed entry over steps of 1e-6 |alpha rho|)
+    np.testing.assert_allclose(out[0], 1.0, atol=1e-6)
+    np.testing.assert_allclose(out[1:], 0.0, atol=1e-6)
 
 
 def test_solid_cells_pass_through(oracle):
