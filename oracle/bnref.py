@@ -168,7 +168,8 @@ def adjoint_fd(s, q, lam, dt: float, h: float = 1e-6) -> np.ndarray:
     """Adjoint of one step with time step dt at state q, by its definition: (dF/dq)^T lam with
     F = step(., dt), the Jacobian taken column by column by central differences.  The perturbation
     of an entry is h times its cell's own scale (|alpha rho| for alpha rho, |alpha rho| x 1 m/s for
-    the momenta, |alpha| for alpha), so that it stays small against gas and liquid values alike;
+    the momenta, so that it stays small against gas and liquid values alike; 1 for alpha, whose
+    perturbation reaches every liquid cell of its column through the free surface);
     the truncation error is O(h^2) away from the scheme's non-smooth points.  One pair of full
     steps per state entry: small grids only."""
     q = _state(s, q)
@@ -177,7 +178,7 @@ def adjoint_fd(s, q, lam, dt: float, h: float = 1e-6) -> np.ndarray:
     for k in range(4):
         for j in range(s.ny):
             for i in range(s.nx):
-                hk = h * (abs(q[3, j, i]) if k == 3 else abs(q[0, j, i]))
+                hk = h * (1.0 if k == 3 else abs(q[0, j, i]))
                 qp = q.copy()
                 qm = q.copy()
                 qp[k, j, i] += hk
