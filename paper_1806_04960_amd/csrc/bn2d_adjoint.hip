@@ -15,7 +15,8 @@
 //                         (each edge state feeds exactly one edge: no accumulation), 18 planes
 //   3. adj_cell_kernel    reverse the reconstruction: adjoints of the 3 x 3 stencil (36 planes)
 //                         and of y0_i (1 plane)
-//   4. adj_col_kernel     sum the y0 adjoints of each column
+//   4. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
+//                         gather adds the blocks' partial sums in order: deterministic)
 //   5. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
 //                         fluid cells whose stencil holds c + the detector's dy/(alpha_l -
 //                         alpha_g) times its column's y0 adjoint (alpha only); solid cells pass
@@ -40,9 +41,11 @@ struct AdjArgs {
     double *rec;            // kRecPlanes planes
     double *fb;             // kFacePlanes planes
     double *wb;             // 36 planes
-    double *y0b;            // 1 plane
-    double *colb;           // nx
+    double *y0b;            // 1 plane (0 for solid cells)
+    double *colb;           // [ceil(ny / kColRows)][nx] partial column sums
 };
+
+constexpr int kColRows = 32;
 
 // plane layout of rec: qW 0-3, qE 4-7, qS 8-11, qN 12-15, e1S 16, e1N 17, aE 18, yS 19, yN 20
 // (the heights of the S/N states: the edge's for a second-order cell, the centre's for a
@@ -231,7 +234,10 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const int i = (int)(c % a.K.nx), j = (int)(c / a.K.nx);
-    if (!fluid_at(a, i, j)) return;
+    if (!fluid_at(a, i, j)) {
+        a.y0b[c] = 0.0;
+        return;
+    }
     double wq[3][3][4];
     int wf[3][3];
     load_stencil(a, i, j, wq, wf);
@@ -267,14 +273,19 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
     a.y0b[c] = yb;
 }
 
-__global__ void adj_col_kernel(AdjArgs a)
+// partial sum of rows [kColRows y, kColRows (y+1)) of column i (grid: columns / 64 x row blocks)
+__global__ __launch_bounds__(64) void adj_col_kernel(AdjArgs a)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= a.K.nx) return;
+    const int j0 = (int)blockIdx.y * kColRows, j1 = min(a.K.ny, j0 + kColRows);
+    double v[kColRows];
+#pragma unroll
+    for (int u = 0; u < kColRows; ++u) v[u] = j0 + u < j1 ? a.y0b[(size_t)(j0 + u) * a.K.nx + i] : 0.0;
     double s = 0.0;
-    for (int j = 0; j < a.K.ny; ++j)
-        if (fluid_at(a, i, j)) s += a.y0b[(size_t)j * a.K.nx + i];
-    a.colb[i] = s;
+#pragma unroll
+    for (int u = 0; u < kColRows; ++u) s += v[u];
+    a.colb[(size_t)blockIdx.y * a.K.nx + i] = s;
 }
 
 __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
@@ -298,7 +309,9 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) out[k] += a.wb[((dj * 3 + di) * 4 + k) * n + m];
             }
-        out[3] += a.K.dy / (a.K.al - a.K.ag) * a.colb[i];
+        double col = 0.0;
+        for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
+        out[3] += a.K.dy / (a.K.al - a.K.ag) * col;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k];
@@ -306,13 +319,15 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
 
 }  // namespace bn
 
-// Launch the five passes on `stream`.  Scratch planes are sized by the caller (kAdjPlanes planes
-// of nx*ny doubles plus nx).
+// Launch the five passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
 namespace bn {
 constexpr int kAdjPlanes = kRecPlanes + kFacePlanes + 36 + 1;
 }
 
-int bn_adjoint_planes() { return bn::kAdjPlanes; }
+size_t bn_adjoint_scratch(int nx, int ny)
+{
+    return (size_t)bn::kAdjPlanes * nx * ny + (size_t)nx * ((ny + bn::kColRows - 1) / bn::kColRows);
+}
 
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
                              const uint8_t *solid, const int *jb, const long long *S, double fix_inv, double dt,
@@ -342,7 +357,8 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     hipLaunchKernelGGL(bn::adj_xedge_kernel, dim3((unsigned)((nxe + 63) / 64)), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_yedge_kernel, dim3((unsigned)((nye + 63) / 64)), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_cell_kernel, dim3(gc64), dim3(64), 0, stream, a);
-    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
+                       0, stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

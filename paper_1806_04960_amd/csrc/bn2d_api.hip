@@ -26,7 +26,7 @@ __global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, dou
 }  // namespace bn
 
 // the discrete adjoint's passes (bn2d_adjoint.hip)
-int bn_adjoint_planes();
+size_t bn_adjoint_scratch(int nx, int ny);
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
                              const uint8_t *solid, const int *jb, const long long *S, double fix_inv, double dt,
                              double *scratch, hipStream_t stream);
@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kOutCols = 60;  // output columns per wavefront (64 lanes minus a 2-column halo each side)
 constexpr int kDefaultRowsPerBlock = 4;
+constexpr int kReduceRows = 8;  // rows per block of the free-surface / CFL reduction of a given state
 
 thread_local std::string g_last_hip_error;
 
@@ -446,7 +447,7 @@ int bn_batch_set_state(bn_batch *b, int32_t member, const double *q_dev)
     int rc = zero_S(b, g, b->m3);
     if (!rc) rc = zero_S(b, g, (b->m3 + 1) % 3);
     if (rc) return rc;
-    const int H = 64;
+    const int H = kReduceRows;
     const dim3 rgrid((g.grid.nx + 63) / 64, (g.grid.ny + H - 1) / H);
     hipLaunchKernelGGL(bn::reduce_kernel, rgrid, dim3(64), 0, b->stream, g.q[b->cur], g.solid,
                        g.S + (size_t)b->m3 * g.grid.nx, g.dev.fix_scale, g.lam + b->m3, g.flag, g.dev.K, H);
@@ -631,9 +632,8 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     bn_batch *b = c->b;
     Grid &g = b->g[0];
     const int nx = g.grid.nx, ny = g.grid.ny;
-    const size_t n = (size_t)nx * ny;
     if (!g.adj) {
-        hipError_t e = hipMalloc(&g.adj, sizeof(double) * ((size_t)bn_adjoint_planes() * n + nx));
+        hipError_t e = hipMalloc(&g.adj, sizeof(double) * bn_adjoint_scratch(nx, ny));
         if (e == hipSuccess) e = hipMalloc(&g.adjS, sizeof(long long) * (nx + 2));
         if (e != hipSuccess) {
             if (g.adj) (void)hipFree(g.adj);
@@ -647,7 +647,7 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     long long *S = g.adjS;
     hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 2 + 255) / 256), dim3(256), 0, b->stream, S, nx + 2);
     HIP_TRY(hipGetLastError());
-    const int H = 64;
+    const int H = kReduceRows;
     hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
                        g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
     HIP_TRY(hipGetLastError());

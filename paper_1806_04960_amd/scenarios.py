@@ -355,5 +355,33 @@ def generic_state(s: Scenario, seed: int, rel: float = 1e-3, vel: float = 0.05) 
     return out
 
 
+def smooth_state(s: Scenario, amp: float = 1e-3, vel: float = 0.05) -> Scenario:
+    """A smooth, physically consistent departure from s.q for trajectory derivative checks: in
+    liquid cells (alpha > 1/2) alpha and alpha rho both scaled by 1 - amp/10 (1 + sin(2 pi x / 0.31
+    + 1.1) sin(2 pi y / 0.19 + 0.4)) (density unchanged), then alpha rho by 1 + amp sin(2 pi x /
+    0.37 + 0.3) sin(2 pi y / 0.23 + 0.7), and a smooth velocity field (vel (1 + 0.5 sin), vel (1 +
+    0.5 cos)); gas cells drift uniformly at (vel, vel).  Neighbouring liquid cells then differ in
+    every component (no limiter min/max ties, as a fluid at rest has), while the gas keeps its
+    density (a noisy gas density makes pressure jumps that the light phase cannot carry)."""
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    q = s.q.copy()
+    fl = s.fluid()
+    liq = fl & (q[3] > 0.5)
+    gas = fl & ~liq
+    frac = 1.0 - 0.1 * amp * (1.0 + np.sin(2 * np.pi * X / 0.31 + 1.1) * np.sin(2 * np.pi * Y / 0.19 + 0.4))
+    q[3] = np.where(liq, q[3] * frac, q[3])
+    wave = np.sin(2 * np.pi * X / 0.37 + 0.3) * np.sin(2 * np.pi * Y / 0.23 + 0.7)
+    ar = np.where(liq, q[0] * frac * (1.0 + amp * wave), q[0])
+    u = np.where(liq, vel * (1.0 + 0.5 * np.sin(2 * np.pi * (X + Y) / 0.41)), np.where(gas, vel, 0.0))
+    v = np.where(liq, vel * (1.0 + 0.5 * np.cos(2 * np.pi * (X - Y) / 0.29)), np.where(gas, vel, 0.0))
+    q[0] = ar
+    q[1] = np.where(fl, ar * u, q[1])
+    q[2] = np.where(fl, ar * v, q[2])
+    out = s.copy()
+    out.q = q
+    out.name = s.name + "_smooth"
+    return out
+
+
 def scaled(builder, nx: int, ny: int, **kw) -> Scenario:
     return builder(nx=nx, ny=ny, **kw)
