@@ -208,9 +208,10 @@ BN_DEV void edge_y_rev(const Consts &K, const double qm[4], double e1m, double a
         R2[k] = gp[k] - gh[k];
         R3[k] = gp[k] - gm[k];
     }
-    R1[2] += b3(K, qm, e1m, aEm, Pm, ym, q12, e1h, aEh, Ph, yh);
-    R2[2] += b3(K, q12, e1h, aEh, Ph, yh, qp, e1p, aEp, Pp, yp);
-    R3[2] += b3(K, qm, e1m, aEm, Pm, ym, qp, e1p, aEp, Pp, yp);
+    const bool grav = y_jump(ym, yp);
+    R1[2] += b3(K, qm, e1m, aEm, Pm, ym, q12, e1h, aEh, Ph, yh, grav);
+    R2[2] += b3(K, q12, e1h, aEh, Ph, yh, qp, e1p, aEp, Pp, yp, grav);
+    R3[2] += b3(K, qm, e1m, aEm, Pm, ym, qp, e1p, aEp, Pp, yp, grav);
     R1[3] += v14 * (q12[3] - qm[3]);
     R2[3] += v34 * (qp[3] - q12[3]);
     R3[3] += 0.5 * (v14 + v34) * d[3];
@@ -331,9 +332,9 @@ BN_DEV double reconstruct_rev(const Consts &K, const double (&wq)[3][3][4], cons
                 phi[dj][di][3] = fluid ? wq[dj][di][3] - aE : fc[3];
             }
         // forward: limited gradients
-        double gxr[4], gyr[4], psi[4], gx[4], gy[4], lim[4], hx[4], hy[4];
+        double gxr[4], gyr[4], psi[4], gx[4], gy[4], lim[4], hm[4];
         int amx[4], amn[4];
-        bool lim_hi[4], use_x[4], rx1[4], ry1[4];
+        bool lim_hi[4], use_x[4], const1[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             gxr[k] = (phi[1][2][k] - phi[1][0][k]) * K.inv2dx;
@@ -353,15 +354,12 @@ BN_DEV double reconstruct_rev(const Consts &K, const double (&wq)[3][3][4], cons
             const double up = mx - fc[k], dn = fc[k] - mn;
             lim_hi[k] = up <= dn;
             lim[k] = fmin(up, dn);
-            hx[k] = fabs(gxr[k] * (0.5 * K.dx));
-            hy[k] = fabs(gyr[k] * (0.5 * K.dy));
-            const double rx = fmin(1.0, lim[k] * rcp(hx[k])), ry = fmin(1.0, lim[k] * rcp(hy[k]));
-            const double px = hx[k] > 0.0 ? rx : 1.0;
-            const double py = hy[k] > 0.0 ? ry : 1.0;
-            rx1[k] = !(hx[k] > 0.0) || !(lim[k] * rcp(hx[k]) < 1.0);  // px is the constant 1
-            ry1[k] = !(hy[k] > 0.0) || !(lim[k] * rcp(hy[k]) < 1.0);
-            use_x[k] = px <= py;
-            psi[k] = fmin(px, py);
+            const double hx = fabs(gxr[k] * (0.5 * K.dx)), hy = fabs(gyr[k] * (0.5 * K.dy));
+            use_x[k] = hx >= hy;  // the difference max(hx, hy) selects
+            hm[k] = fmax(hx, hy);
+            const double r = fmin(1.0, lim[k] * rcp(hm[k]));
+            psi[k] = hm[k] > 0.0 ? r : 1.0;
+            const1[k] = !(hm[k] > 0.0) || !(lim[k] * rcp(hm[k]) < 1.0);  // psi is the constant 1
             gx[k] = psi[k] * gxr[k];
             gy[k] = psi[k] * gyr[k];
         }
@@ -490,19 +488,13 @@ BN_DEV double reconstruct_rev(const Consts &K, const double (&wq)[3][3][4], cons
             double gxrb = psi[k] * gxb[k], gyrb = psi[k] * gyb[k];
             const double psib = gxr[k] * gxb[k] + gyr[k] * gyb[k];
             double limb = 0.0;
-            // psi = min(px, py); px = min(1, lim / hx) unless that is the constant 1
-            if (use_x[k]) {
-                if (!rx1[k]) {
-                    const double ih = rcp(hx[k]);
-                    limb += psib * ih;
-                    gxrb -= psib * lim[k] * ih * ih * sgn(gxr[k]) * (0.5 * K.dx);
-                }
-            } else {
-                if (!ry1[k]) {
-                    const double ih = rcp(hy[k]);
-                    limb += psib * ih;
-                    gyrb -= psib * lim[k] * ih * ih * sgn(gyr[k]) * (0.5 * K.dy);
-                }
+            // psi = min(1, lim / max(hx, hy)) unless that is the constant 1
+            if (!const1[k]) {
+                const double ih = rcp(hm[k]);
+                limb += psib * ih;
+                const double hmb = -psib * lim[k] * ih * ih;
+                if (use_x[k]) gxrb += hmb * sgn(gxr[k]) * (0.5 * K.dx);
+                else gyrb += hmb * sgn(gyr[k]) * (0.5 * K.dy);
             }
             // lim = min(max - fc, fc - min)
             if (lim_hi[k]) {

@@ -143,6 +143,7 @@ bn::Consts make_consts(const bn_grid &grid, const bn_params &p)
     K.inv2dx = 1.0 / (2.0 * K.dx);
     K.inv2dy = 1.0 / (2.0 * K.dy);
     K.inv_rho0 = 1.0 / p.rho0;
+    K.inv_dal = 1.0 / (p.alpha_liq - p.alpha_gas);
     return K;
 }
 

@@ -65,6 +65,7 @@ Consts make_consts(int nx, int ny, double x0, double x1, double y0, double y1, d
     K.so_thr = 10.0 * ag;
     K.inv_dx = 1.0 / K.dx; K.inv_dy = 1.0 / K.dy; K.inv2dx = 1.0 / (2.0 * K.dx); K.inv2dy = 1.0 / (2.0 * K.dy);
     K.inv_rho0 = 1.0 / rho0;
+    K.inv_dal = 1.0 / (al - ag);
     return K;
 }
 

@@ -31,6 +31,7 @@ struct Consts {
     double e_uph, e_dnh;   // exp(-a dy/2), exp(+a dy/2): ratio to the upper / lower edge
     double so_thr;         // 10 alpha_gas: second-order threshold (Sec. 3.4)
     double inv_dx, inv_dy, inv2dx, inv2dy, inv_rho0;
+    double inv_dal;        // 1 / (alpha_l - alpha_g)
 };
 
 // Cell flags: fluid, outside the grid on a side, and (F_TX, F_TY) outside across a transmissive
@@ -159,20 +160,27 @@ BN_DEV real_t press_fluct(const Consts &K, const real_t q[4], real_t e1, real_t 
 
 // Well-balanced b_3 on one sub-interval (Sec. 3.3): fluctuation pressure jump plus the gravity
 // term of the fluctuations, (mean(alpha) mean(rho) - mean(alpha^E) mean(rho^E)) g (y_b - y_a).
+// `grav` is false when the gravity part vanishes exactly (ya == yb) wherever it is evaluated
+// together (a whole wavefront on the device), which skips it.
 BN_DEV real_t b3(const Consts &K, const real_t qa[4], real_t e1a, real_t aEa, real_t Pa,
-                                     real_t ya, const real_t qb[4], real_t e1b, real_t aEb, real_t Pb, real_t yb)
+                                     real_t ya, const real_t qb[4], real_t e1b, real_t aEb, real_t Pb, real_t yb,
+                                     bool grav)
 {
-    // (the gravity part vanishes exactly when ya == yb; the kernel computes it anyway, without a
-    // branch, while the operation count skips it as the scheme does)
-#ifdef BN2D_HOST_COUNT
-    if (yb == ya) return Pb - Pa;
-#endif
+    if (!grav) return Pb - Pa;
     const real_t abar = 0.5 * (qa[3] + qb[3]);
     const real_t rbar = 0.5 * (qa[0] * rcp(qa[3]) + qb[0] * rcp(qb[3]));
     const real_t aEbar = 0.5 * (aEa + aEb);
     const real_t rEbar = 0.5 * (e1a * rcp(aEa) + e1b * rcp(aEb));
     return (Pb - Pa) + (abar * rbar - aEbar * rEbar) * K.g * (yb - ya);
 }
+
+// Whether the states of a y-edge sit at different heights: per lane on the host, for the whole
+// wavefront on the device (a uniform branch).
+#ifdef BN2D_HOST_COUNT
+BN_DEV bool y_jump(real_t ym, real_t yp) { return ym != yp; }
+#else
+BN_DEV bool y_jump(double ym, double yp) { return __ballot(ym != yp) != 0ull; }
+#endif
 
 // y-edge: well-balanced Osher-Romberg (Sec. 3.3, Romberg l = 3 of Sec. 3.1):
 //   V = 4/3 sign(A2(Phi(1/4))) R(0,1/2) + 4/3 sign(A2(Phi(3/4))) R(1/2,1) - 1/3 sign(A2(Phi(1/2))) R(0,1)
@@ -209,9 +217,11 @@ BN_DEV void edge_y(const Consts &K, const real_t qm[4], real_t e1m, real_t aEm, 
         R2[k] = gp[k] - gh[k];
         R3[k] = gp[k] - gm[k];
     }
-    R1[2] += b3(K, qm, e1m, aEm, Pm, ym, q12, e1h, aEh, Ph, yh);
-    R2[2] += b3(K, q12, e1h, aEh, Ph, yh, qp, e1p, aEp, Pp, yp);
-    R3[2] += b3(K, qm, e1m, aEm, Pm, ym, qp, e1p, aEp, Pp, yp);
+    // both states at one height (every edge between second-order cells): no gravity term
+    const bool grav = y_jump(ym, yp);
+    R1[2] += b3(K, qm, e1m, aEm, Pm, ym, q12, e1h, aEh, Ph, yh, grav);
+    R2[2] += b3(K, q12, e1h, aEh, Ph, yh, qp, e1p, aEp, Pp, yp, grav);
+    R3[2] += b3(K, qm, e1m, aEm, Pm, ym, qp, e1p, aEp, Pp, yp, grav);
     R1[3] += v14 * (q12[3] - qm[3]);
     R2[3] += v34 * (qp[3] - q12[3]);
     R3[3] += 0.5 * (v14 + v34) * d[3];
@@ -321,10 +331,11 @@ BN_DEV void reconstruct(const Consts &K, const S &st, int j, real_t y0c, real_t 
             }
         const real_t lim = fmin(mx - fc[k], fc[k] - mn);
         const real_t hx = fabs(gxr * (0.5 * K.dx)), hy = fabs(gyr * (0.5 * K.dy));
-        const real_t rx = fmin(1.0, lim * rcp(hx)), ry = fmin(1.0, lim * rcp(hy));  // discarded if h = 0
-        const real_t px = hx > 0.0 ? rx : 1.0;
-        const real_t py = hy > 0.0 ? ry : 1.0;
-        const real_t psi = fmin(px, py);
+        // Psi = min over the four midpoints of min(1, lim / |d|) = min(1, lim / max(hx, hy)) (lim >= 0),
+        // 1 where both differences vanish
+        const real_t hm = fmax(hx, hy);
+        const real_t r = fmin(1.0, lim * rcp(hm));  // discarded if hm = 0
+        const real_t psi = hm > 0.0 ? r : 1.0;
         gx[k] = psi * gxr;
         gy[k] = psi * gyr;
     }
@@ -406,7 +417,7 @@ BN_DEV void update_finish(const real_t X[4], const real_t DpS[4], const real_t D
 }
 
 // Free-surface detector term of a fluid cell (Sec. 3.5) and its CFL rate (|u|+c)/dx + (|v|+c)/dy.
-BN_DEV real_t detector_term(const Consts &K, const real_t q[4]) { return (q[3] - K.ag) / (K.al - K.ag); }
+BN_DEV real_t detector_term(const Consts &K, const real_t q[4]) { return (q[3] - K.ag) * K.inv_dal; }
 
 BN_DEV real_t cfl_rate(const Consts &K, const real_t q[4])
 {
