@@ -80,9 +80,23 @@ __device__ __forceinline__ unsigned long long load_word(unsigned long long *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double shfl_from_left(double v) { return __shfl_up(v, 1, 64); }
-__device__ __forceinline__ double shfl_from_right(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ int shfl_from_right(int v) { return __shfl_down(v, 1, 64); }
+// Neighbour lanes through DPP whole-wavefront shifts (a VALU move, no LDS round trip): lane L
+// receives lane L-1 (from_left) or L+1 (from_right); the end lanes keep their own value (they are
+// halo lanes whose results are discarded).
+__device__ __forceinline__ int shfl_from_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int shfl_from_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ double shfl_from_left(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = shfl_from_left((int)(b & 0xFFFFFFFFll)), hi = shfl_from_left((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double shfl_from_right(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = shfl_from_right((int)(b & 0xFFFFFFFFll)), hi = shfl_from_right((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 __device__ __forceinline__ double wave_incl_scan(double v)
 {
