@@ -164,21 +164,22 @@ def run(s, q, n_steps: int):
     return q, t.value, dt.value
 
 
-def adjoint_fd(s, q, lam, dt: float, h: float = 1e-6) -> np.ndarray:
+def adjoint_fd(s, q, lam, dt: float, h=1e-6) -> np.ndarray:
     """Adjoint of one step with time step dt at state q, by its definition: (dF/dq)^T lam with
     F = step(., dt), the Jacobian taken column by column by central differences.  The perturbation
     of an entry is h times its cell's own scale (|alpha rho| for alpha rho, |alpha rho| x 1 m/s for
     the momenta, so that it stays small against gas and liquid values alike; 1 for alpha, whose
     perturbation reaches every liquid cell of its column through the free surface);
     the truncation error is O(h^2) away from the scheme's non-smooth points.  One pair of full
-    steps per state entry: small grids only."""
+    steps per state entry: small grids only.  h: one relative step, or one per component."""
     q = _state(s, q)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
+    hs = np.broadcast_to(np.asarray(h, dtype=np.float64), (4,))
     out = np.zeros_like(q)
     for k in range(4):
         for j in range(s.ny):
             for i in range(s.nx):
-                hk = h * (1.0 if k == 3 else abs(q[0, j, i]))
+                hk = hs[k] * (1.0 if k == 3 else abs(q[0, j, i]))
                 qp = q.copy()
                 qm = q.copy()
                 qp[k, j, i] += hk
