@@ -61,6 +61,25 @@ def build_workload(name):
     raise ValueError(name)
 
 
+def attainable_peaks():
+    """Measured on this GPU: FP64 FMA rate (FLOP/s) and triad HBM bandwidth (B/s), from the probe
+    library, or None where it is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1806_04960_amd", "libbn2d_probe.so")
+    if not os.path.exists(path):
+        return None
+    L = ctypes.CDLL(path)
+    L.bn_probe_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.bn_probe_triad.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    f, b = ctypes.c_double(), ctypes.c_double()
+    out = {}
+    if L.bn_probe_fma(256 * 4 * 8, 200, 5, ctypes.byref(f)) == 0:
+        out["fp64_fma_tflops"] = f.value / 1e12
+    if L.bn_probe_triad(1 << 27, 5, ctypes.byref(b)) == 0:
+        out["triad_tb_per_s"] = b.value / 1e12
+    return out
+
+
 def cpu_baseline(s, steps):
     """The CPU oracle, single thread, on `steps` full steps of the same workload from its initial
     state (a bounded sample of the timed run)."""
@@ -405,6 +424,12 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                 "flops_per_cell_update": flops_per_launch / cells, "kernel_ms": launch_ms,
                 "hbm_frac_at_algorithmic_bytes": cells * STATE_BYTES_PER_CELL / (launch_ms / 1e3) / PEAK_HBM}
+
+    peaks = attainable_peaks()
+    if peaks:
+        roofline["attainable"] = peaks
+        if "fp64_fma_tflops" in peaks:
+            roofline["frac_of_attainable"] = achieved / 1e12 / peaks["fp64_fma_tflops"]
 
     line = {
         "metric": "FP64 cell updates/sec",

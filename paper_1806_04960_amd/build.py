@@ -1,10 +1,14 @@
-"""Build the HIP library ``libbn2d.so`` for gfx950 (in-tree, so it travels with the sources)."""
+"""Build the HIP library ``libbn2d.so`` for gfx950 (in-tree, so it travels with the sources), and
+the attainable-peak probes ``libbn2d_probe.so`` that ``bench.py`` uses for the roofline."""
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "csrc", f) for f in ("bn2d_step.hip", "bn2d_adjoint.hip", "bn2d_api.hip")]
 LIB = os.path.join(HERE, "libbn2d.so")
+# attainable-peak probes for the roofline (measurement only)
+PROBE_SRC = [os.path.join(HERE, "csrc", "bn2d_probe.hip")]
+PROBE_LIB = os.path.join(HERE, "libbn2d_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -14,13 +18,18 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SRC]
+def _compile(srcs, lib, verbose):
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(SRC, LIB, verbose)
+    _compile(PROBE_SRC, PROBE_LIB, verbose)
     return LIB
 
 
