@@ -101,7 +101,8 @@ int bn_status(bn_ctx *ctx);
 
 /* Launch shape of the step kernel.  Wavefronts march strips of 60 columns and claim rows in blocks
  * of rows_per_block (1..4096, 0 = default 4); the launch is persistent with `wavefronts`
- * wavefronts (1..65536, 0 = default: as many as the device holds at once).  Results are bitwise the same
+ * wavefronts (1..65536, 0 = default: as many as the device holds at once, or fewer for a small grid,
+ * about one per 4.5 rows of 60-column strips, a power of two, at least 256).  Results are bitwise the same
  * for every shape: each cell is computed by the same arithmetic whatever wavefront does it, and
  * the free-surface integral is summed exactly (64-bit fixed point).  Synchronises the stream. */
 int bn_set_launch(bn_ctx *ctx, int32_t rows_per_block, int32_t wavefronts);

@@ -496,14 +496,15 @@ BN_DEV double reconstruct_rev(const Consts &K, const double (&wq)[3][3][4], cons
                 if (use_x[k]) gxrb += hmb * sgn(gxr[k]) * (0.5 * K.dx);
                 else gyrb += hmb * sgn(gyr[k]) * (0.5 * K.dy);
             }
-            // lim = min(max - fc, fc - min)
-            if (lim_hi[k]) {
-                phib[amx[k] / 3][amx[k] % 3][k] += limb;
-                fcb[k] -= limb;
-            } else {
-                fcb[k] += limb;
-                phib[amn[k] / 3][amn[k] % 3][k] -= limb;
-            }
+            // lim = min(max - fc, fc - min): to the selected extreme (a select per stencil entry, so
+            // that phib stays in registers)
+            const int ext = lim_hi[k] ? amx[k] : amn[k];
+            const double eb = lim_hi[k] ? limb : -limb;
+            fcb[k] -= eb;
+#pragma unroll
+            for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+                for (int di = 0; di < 3; ++di) phib[dj][di][k] += ext == dj * 3 + di ? eb : 0.0;
             phib[1][2][k] += gxrb * K.inv2dx;
             phib[1][0][k] -= gxrb * K.inv2dx;
             phib[2][1][k] += gyrb * K.inv2dy;

@@ -64,6 +64,16 @@ int default_wavefronts()
     return cus * per_cu;
 }
 
+// The default launch: all resident wavefronts, or fewer for little work, about one per 4.5 strip
+// rows (a power of two, at least 256), since every range costs two halo rows (measured on dam
+// breaks: 256 for 256x128, 512 for 512x256, all 2048 resident ones from 2048x1024 on).
+int sized_wavefronts(int resident, long long strip_rows)
+{
+    long long p = 256;
+    while (p * 2 <= (long long)(strip_rows / 4.5)) p *= 2;
+    return (int)std::min<long long>(resident, p);
+}
+
 // One grid: its parameters and device buffers.  `dev` mirrors what the kernels read.
 struct Grid {
     bn_grid grid;
@@ -425,7 +435,7 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
         g_last_hip_error = std::string("bn_batch_create: ") + hipGetErrorString(e);
         return fail(BN_EHIP);
     }
-    b->P_default = default_wavefronts();
+    b->P_default = sized_wavefronts(default_wavefronts(), b->nrows);
     b->P = b->P_default;
     int rc = set_shape(b);
     if (!rc) rc = write_tables(b);

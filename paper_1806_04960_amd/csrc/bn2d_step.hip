@@ -666,6 +666,7 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
     int bad = 0;
     if (i < K.nx) {
         const int ja = (int)blockIdx.y * H, je = min(K.ny, ja + H);
+#pragma unroll 8
         for (int j = ja; j < je; ++j) {
             const size_t cidx = (size_t)j * K.nx + i;
             if (solid && solid[cidx]) continue;
