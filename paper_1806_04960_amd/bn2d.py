@@ -326,3 +326,48 @@ def step_function():
             return None, lam, None
 
     return StepFn
+
+
+def tune_launch(obj, steps: int = 30, shapes=None):
+    """Choose the launch shape (rows per claim, wavefronts) of a ``Simulation`` or ``Batch`` by
+    timing ``steps`` steps of each candidate on its current state(s), set the fastest and restore
+    the state(s) (through set_state, which also resets the elapsed times).  Results do not depend
+    on the shape, only the time per step does.  Returns (rows_per_block, wavefronts, {shape: ms})."""
+    import torch
+
+    batch = isinstance(obj, Batch)
+    members = range(len(obj)) if batch else [None]
+    saved = [obj.get_state(k) for k in members] if batch else [obj.get_state()]
+
+    def restore():
+        if batch:
+            for k, q in zip(members, saved):
+                obj.set_state(k, q)
+        else:
+            obj.set_state(saved[0])
+
+    set_launch = (lambda r, w: check(lib().bn_batch_set_launch(obj._b, r, w), "bn_batch_set_launch")) if batch \
+        else obj.set_launch
+    set_launch(0, 0)
+    r0, w0 = obj.launch()
+    if shapes is None:
+        waves = sorted({max(64, w0 // 4), max(64, w0 // 2), w0, min(65536, 2 * w0)} | {w for w in (512, 1024, 2048)
+                                                                                         if w <= 2 * w0})
+        shapes = [(r, w) for w in waves for r in (2, 4, 8)]
+    times = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for r, w in shapes:
+        set_launch(int(r), int(w))
+        restore()
+        obj.run(3)
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record()
+        obj.run(steps)
+        b.record()
+        torch.cuda.synchronize()
+        times[(r, w)] = a.elapsed_time(b) / steps
+    best = min(times, key=times.get)
+    set_launch(int(best[0]), int(best[1]))
+    restore()
+    return best[0], best[1], times

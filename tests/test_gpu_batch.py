@@ -144,3 +144,24 @@ def test_run_before_every_member_has_a_state_is_rejected(bn, torch_cuda):
         b.set_state(0, torch_cuda.from_numpy(members[0].q).cuda())
         with pytest.raises(bn.BnError):
             b.run(1)
+
+
+def test_tuned_launch_is_the_fastest_candidate_and_changes_no_result(bn, torch_cuda):
+    s = sc.dam_break(3, 300, 150)
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch_cuda.from_numpy(s.q).cuda())
+        rows, waves, times = bn.tune_launch(sim, steps=10, shapes=[(4, 256), (4, 2048), (2, 512)])
+        assert (rows, waves) == min(times, key=times.get)
+        assert sim.launch() == (rows, waves)
+        sim.run(15)
+        q = sim.get_state().cpu().numpy()
+    with bn.Simulation(s) as ref:
+        ref.set_state(torch_cuda.from_numpy(s.q).cuda())
+        ref.run(15)
+        assert np.array_equal(q, ref.get_state().cpu().numpy())
+    members = small_members()[:3]
+    with bn.Batch(members) as b:
+        for k, m in enumerate(members):
+            b.set_state(k, torch_cuda.from_numpy(m.q).cuda())
+        rows, waves, times = bn.tune_launch(b, steps=5, shapes=[(4, 128), (8, 1024)])
+        assert b.launch() == (rows, waves)
