@@ -64,7 +64,9 @@ typedef struct bn_ctx bn_ctx;
 /* Create a context.  solid: host array of nx*ny bytes (row-major, 1 = solid cell removed from
  * the domain, Sec. 5.1) or NULL; each column's solid cells must form one run attached to the
  * bottom (else BN_EUNSUPPORTED), as the free-surface detector of Sec. 3.5 integrates alpha
- * from the top of that run.  hip_stream: a hipStream_t or NULL.  Synchronous. */
+ * from the top of that run.  hip_stream: a hipStream_t or NULL.  Synchronous.  Sizes: at most
+ * 32767 column strips of 60 (nx <= 1966020) and ny <= 16711680 (0xFF0000), the fields of the
+ * step kernel's range descriptors; larger grids give BN_EINVAL. */
 int bn_create(const bn_grid *grid, const bn_params *params, const uint8_t *solid, void *hip_stream,
               bn_ctx **out);
 

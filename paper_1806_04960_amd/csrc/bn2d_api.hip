@@ -343,10 +343,13 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
     *out = nullptr;
     if (count <= 0 || count > 0x7FFF || !grids || !params) return BN_EINVAL;
     std::vector<std::vector<int>> jbs(count);
+    long long total_strips = 0;
     for (int k = 0; k < count; ++k) {
         const int rc = check_grid(&grids[k], &params[k], solids ? solids[k] : nullptr, jbs[k]);
         if (rc) return rc;
+        total_strips += (grids[k].nx + kOutCols - 1) / kOutCols;
     }
+    if (total_strips > 0x7FFF) return BN_EINVAL;  // the strip field of a range descriptor
     bn_batch *b = new (std::nothrow) bn_batch();
     if (!b) return BN_ENOMEM;
     b->stream = (hipStream_t)hip_stream;
@@ -418,7 +421,6 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
         b->nrows += (long long)M.nstrips * ny;
         for (int s = 0; s < M.nstrips; ++s) strips.push_back({k, s, ny, 0, M.cost0 + (long long)s * ny});
     }
-    if (b->nstrips > 0x7FFF) return fail(BN_EINVAL);
     ALLOC(b->members, sizeof(bn::Member) * count);
     ALLOC(b->ctl, sizeof(bn::Control) * 6);
     ALLOC(b->nranges, sizeof(int) * 2);

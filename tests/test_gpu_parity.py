@@ -221,3 +221,46 @@ def test_full_size_dam_break_conserves_mass_over_bench_steps(bn, torch_cuda):
     m1 = math.fsum(q[0][fl].ravel())
     assert abs(m1 - m0) / m0 < 1e-12
     assert q[3][fl].min() > 0 and q[3][fl].max() <= 1.0
+
+
+# ---- the largest grids the range descriptors address ------------------------------------------
+# A range descriptor holds a 15-bit global strip index and 24-bit row fields, so a grid may have
+# at most 32767 column strips of 60 outputs and 0xFF0000 rows (room for one claim past the end).
+
+MAX_STRIPS, MAX_ROWS = 0x7FFF, 0xFF0000
+
+
+def _one_step_on_sampled_cells(oracle, bn, torch, s, extra_cells, seed):
+    lam, dt = oracle.cfl(s, s.q)
+    with bn.Simulation(s) as sim:
+        sim.set_state(torch.from_numpy(s.q).cuda())
+        print(f"{s.name} {s.nx}x{s.ny}: launch {sim.launch()}", flush=True)
+        sim.run(1)
+        t, _ = sim.time()  # elapsed time: the dt of the step taken
+        q1 = sim.get_state().cpu().numpy()
+    assert abs(t - dt) <= 1e-14 * dt
+    cells = np.unique(np.concatenate([_sample_cells(s, 4000, seed), extra_cells]))
+    ref = oracle.step_cells(s, s.q, dt, cells)
+    assert_parity(s, q1.reshape(4, -1)[:, cells], ref)
+    return q1
+
+
+def test_widest_grid(oracle, bn, torch_cuda):
+    s = sc.random_state(sc.rest_flat(MAX_STRIPS * 60, 4), seed=11, amp=0.002, vel=0.02)
+    # the first and last strip, strips at the range boundaries of a spanned partition and a whole
+    # row across every strip seam
+    seams = np.arange(1, MAX_STRIPS) * 60
+    row1 = np.concatenate([seams - 1, seams]) + s.nx
+    q1 = _one_step_on_sampled_cells(oracle, bn, torch_cuda, s, np.concatenate([np.arange(130), row1]), 12)
+    assert np.isfinite(q1).all()
+
+
+def test_tallest_grid(oracle, bn, torch_cuda):
+    s = sc.random_state(sc.rest_flat(2, MAX_ROWS), seed=13, amp=0.002, vel=0.02)
+    # rows around the boundaries of the first step's row ranges (an even split among wavefronts
+    # for any wavefront count dividing 4096), the free surface and the top and bottom
+    bounds = np.unique((np.arange(1, 4096) * MAX_ROWS) // 4096)
+    rows = np.concatenate([bounds + d for d in (-2, -1, 0, 1)] + [np.arange(3), MAX_ROWS - 1 - np.arange(3),
+                                                                      MAX_ROWS // 2 + np.arange(-3, 3)])
+    cells = np.concatenate([rows * 2, rows * 2 + 1])
+    _one_step_on_sampled_cells(oracle, bn, torch_cuda, s, cells, 14)

@@ -128,3 +128,19 @@ def test_batch_null_arguments_and_bad_counts():
     assert L.bn_batch_set_launch(None, 0, 0) == bn2d.BN_EINVAL
     assert L.bn_batch_get_launch(None, None, None) == bn2d.BN_EINVAL
     L.bn_batch_destroy(None)
+
+
+@pytest.mark.parametrize("nx,ny", [(0x7FFF * 60 + 1, 4), (4, 0xFF0000 + 1)])
+def test_create_rejects_grids_beyond_the_descriptor_fields(nx, ny):
+    s = sc.uniform_tank(4, 4)
+    s.nx, s.ny = nx, ny
+    rc, ctx = _create(s)
+    assert rc == bn2d.BN_EINVAL and not ctx.value
+
+
+def test_batch_create_rejects_too_many_strips_in_total():
+    # each member alone is within the limit, together they are not; rejected before allocating
+    a = sc.uniform_tank(4, 4)
+    a.nx = 0x7FFF * 60
+    rc, out = _batch_create([a, sc.uniform_tank(4, 4)])
+    assert rc == bn2d.BN_EINVAL and not out.value
