@@ -352,7 +352,7 @@ def main():
     ap.add_argument("--fd-directions", type=int, default=4, help="gradient checks (workload adjoint)")
     ap.add_argument("--rows", type=int, default=None, help="rows per claimed block of the step kernel")
     ap.add_argument("--wavefronts", type=int, default=None, help="wavefronts of the persistent step kernel")
-    ap.add_argument("--cpu-baseline-steps", type=int, default=4)
+    ap.add_argument("--cpu-baseline-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES bytes (calibrates the HBM byte counters)")
