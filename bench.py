@@ -232,27 +232,8 @@ def adjoint_main(args):
         for _ in range(N):
             sim.step(dt)
 
-    def gradient():
-        ck = [q0.clone()]
-        sim.set_state(q0)
-        for k in range(N):
-            sim.step(dt)
-            if (k + 1) % seg == 0 and k + 1 < N:
-                ck.append(sim.get_state())
-        lam = torch.zeros_like(q0)
-        buf = [None] * seg
-        for c in range(len(ck) - 1, -1, -1):
-            n0 = c * seg
-            m = min(seg, N - n0)
-            sim.set_state(ck[c])
-            buf[0] = ck[c]
-            for k in range(1, m):
-                sim.step(dt)
-                buf[k] = sim.get_state()
-            for k in range(m - 1, -1, -1):
-                lam = lam + w  # dJ/dQ^{n0+k+1}
-                lam = sim.adjoint_step(buf[k], lam, dt)
-        return lam
+    def gradient(q_init=None):
+        return bn2d.trajectory_gradient(sim, q0 if q_init is None else q_init, dt, N, w, seg)
 
     forward_plain()
     gradient()
@@ -290,35 +271,54 @@ def adjoint_main(args):
     print(f"# forward {fwd_ms:.2f} ms, gradient {grad_ms:.2f} ms (x{grad_ms / fwd_ms:.2f}); step {step_ms*1e3:.1f} us, "
           f"adjoint step {adj_ms*1e3:.1f} us", file=sys.stderr, flush=True)
 
-    # gradient check along seeded patch directions of the initial state (difference quotients at h
-    # and h/2; their disagreement estimates the quotient's own error, large where the trajectory
-    # crosses one of the scheme's kinks: the liquid at rest sits on the limiter's min/max ties)
+    # gradient checks: dJ/dq0 along seeded patch directions of the initial state, and dJ/dtheta
+    # (the 64 profile values, chained through the state's construction) along seeded directions;
+    # difference quotients at h and h/2, whose disagreement estimates the quotient's own error
+    # (large where the trajectory crosses one of the scheme's kinks: the liquid at rest sits on the
+    # limiter's min/max ties).  Each kind alternately from the workload's initial state and from a
+    # smooth departure from it (see scenarios.smooth_state).
     rng = np.random.default_rng(0)
     checks = []
     scale = np.stack([np.abs(s.q[0])] * 3 + [np.abs(s.q[3])]) * s.fluid()
-    smooth = torch.from_numpy(sc.smooth_state(s).q).cuda()
-    q_init = q0
-    g_smooth = None
+    q_smooth = torch.from_numpy(sc.smooth_state(s).q).cuda()
+    g_of = {"initial": g.cpu().numpy(), "smooth": gradient(q_smooth).cpu().numpy()}
+    q_of = {"initial": q0, "smooth": q_smooth}
+    theta0 = np.asarray(s.meta["theta"])
+    gth_of = {"initial": sc.wall_impact_theta_vjp(s, g_of["initial"]),
+              "smooth": sc.wall_impact_theta_vjp(s, sc.smooth_state_vjp(s, g_of["smooth"]))}
+
+    def q_theta(theta, kind):
+        st = sc.wall_impact(0, theta=theta)
+        return torch.from_numpy((sc.smooth_state(st) if kind == "smooth" else st).q).cuda()
+
+    def record(entry, ad, fd1, fd2):
+        spread = abs(fd1 - fd2) / abs(fd2) if fd2 else None
+        # a quotient that moves by more than 1e-4 between h and h/2 straddles a kink: reported,
+        # not a check of the gradient
+        entry.update({"adjoint": ad, "fd": fd2, "rel": abs(ad - fd2) / abs(fd2) if fd2 else None,
+                      "fd_h_vs_h2": spread, "kink": spread is None or spread > 1e-4})
+        checks.append(entry)
+        print(f"# check {len(checks) - 1}: {entry}", file=sys.stderr, flush=True)
+
     for m in range(2 * args.fd_directions):
-        # alternately from the workload's initial state and from a smooth departure from it (see
-        # scenarios.smooth_state); patches in the reservoir (rows below 0.75 m, left of the wall)
-        from_smooth = m % 2 == 1
-        q0 = smooth if from_smooth else q_init
-        if from_smooth and g_smooth is None:
-            g_smooth = gradient().cpu().numpy()
-        gn = g_smooth if from_smooth else g.cpu().numpy()
+        kind = "smooth" if m % 2 else "initial"
+        # a patch in the reservoir (rows below 0.75 m, left of the wall)
         j0, i0 = int(rng.integers(0, 96 - 24)), int(rng.integers(0, iw - 24))
         d = np.zeros_like(s.q)
         d[:, j0:j0 + 24, i0:i0 + 24] = rng.normal(size=(4, 24, 24))
         d *= scale
         dd = torch.from_numpy(d).cuda()
-        h = 1e-7
-        fd1 = (loss(q0 + h * dd) - loss(q0 - h * dd)) / (2 * h)
-        fd2 = (loss(q0 + h / 2 * dd) - loss(q0 - h / 2 * dd)) / h
-        ad = float(np.sum(gn * d))
-        checks.append({"state": "smooth" if from_smooth else "initial", "patch": [j0, i0], "adjoint": ad,
-                       "fd": fd2, "rel": abs(ad - fd2) / abs(fd2), "fd_h_vs_h2": abs(fd1 - fd2) / abs(fd2)})
-        print(f"# direction {m}: {checks[-1]}", file=sys.stderr, flush=True)
+        qa, h = q_of[kind], 1e-7
+        fd1 = (loss(qa + h * dd) - loss(qa - h * dd)) / (2 * h)
+        fd2 = (loss(qa + h / 2 * dd) - loss(qa - h / 2 * dd)) / h
+        record({"wrt": "q0", "state": kind, "patch": [j0, i0]}, float(np.sum(g_of[kind] * d)), fd1, fd2)
+    for m in range(2 * args.fd_directions):
+        kind = "smooth" if m % 2 else "initial"
+        dth = rng.normal(size=theta0.size)
+        h = 1e-6
+        fd1 = (loss(q_theta(theta0 + h * dth, kind)) - loss(q_theta(theta0 - h * dth, kind))) / (2 * h)
+        fd2 = (loss(q_theta(theta0 + h / 2 * dth, kind)) - loss(q_theta(theta0 - h / 2 * dth, kind))) / h
+        record({"wrt": "theta", "state": kind}, float(gth_of[kind] @ dth), fd1, fd2)
     sim.close()
     line = {
         "metric": "FP64 cell updates/sec",
@@ -336,7 +336,8 @@ def adjoint_main(args):
         "config": {"workload": f"discrete adjoint, wall impact {s.nx}x{s.ny} seed 0, {N} steps of fixed dt, "
                                f"checkpoints every {seg}", "nx": s.nx, "ny": s.ny},
         "adjoint": {"forward_ms": fwd_ms, "gradient_ms": grad_ms, "cost_ratio": grad_ms / fwd_ms,
-                    "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3, "fd_checks": checks},
+                    "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3,
+                    "grad_theta_norm": float(np.linalg.norm(gth_of["initial"])), "fd_checks": checks},
     }
     print(json.dumps(line), flush=True)
 

@@ -328,6 +328,48 @@ def step_function():
     return StepFn
 
 
+def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False):
+    """Gradient of J = sum_{n=1..N} <weights, Q^n> over N steps of fixed length dt from q0 with
+    respect to q0, by the discrete adjoint (``bn_adjoint_step``): the forward run keeps the state
+    every ``segment`` steps, then each segment, last first, is recomputed from its checkpoint and
+    reversed step by step.  Memory: N/segment + segment states.  Returns dJ/dq0, or (J, dJ/dq0) with
+    ``with_loss`` (J then also costs a reduction per forward step).  Leaves the context at the start
+    of the first segment."""
+    import torch
+
+    N, seg = int(n_steps), int(segment)
+    if N < 0 or seg < 1:
+        raise ValueError("n_steps >= 0 and segment >= 1 required")
+    w = weights.contiguous()
+    ck = [q0.detach().clone()]
+    sim.set_state(ck[0])
+    J = torch.zeros((), dtype=torch.float64, device=q0.device)
+    for k in range(N):
+        sim.step(dt)
+        last = k + 1 == N
+        if with_loss or ((k + 1) % seg == 0 and not last):
+            q = sim.get_state()
+            if with_loss:
+                J += (w * q).sum()
+            if (k + 1) % seg == 0 and not last:
+                ck.append(q)
+    lam = torch.zeros_like(ck[0])
+    buf = [None] * seg
+    for c in range(len(ck) - 1, -1, -1):
+        n0 = c * seg
+        m = min(seg, N - n0)
+        sim.set_state(ck[c])
+        buf[0] = ck[c]
+        for k in range(1, m):
+            sim.step(dt)
+            buf[k] = sim.get_state()
+        for k in range(m - 1, -1, -1):
+            lam = lam + w  # dJ/dQ^{n0+k+1}
+            lam = sim.adjoint_step(buf[k], lam, dt)
+    sim.set_state(ck[0])
+    return (float(J), lam) if with_loss else lam
+
+
 def tune_launch(obj, steps: int = 30, shapes=None):
     """Choose the launch shape (rows per claim, wavefronts) of a ``Simulation`` or ``Batch`` by
     timing ``steps`` steps of each candidate on its current state(s), set the fastest and restore

@@ -245,16 +245,17 @@ def ensemble(seed: int = 0, count: int = 64, sizes=ENSEMBLE_SIZES):
     return out
 
 
-def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64):
+def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, theta=None):
     """Reservoir released against a wall, the adjoint workload: [0,4] x [0,2], free-surface profile
     h(x) piecewise linear through theta_k = 0.6 + 0.1 U(-1, 1) at x_k = 3.5 k / (n_theta - 1);
     alpha is the liquid volume fraction of each cell below h(x_i) (two-level away from the surface,
     fractional in the cell the surface cuts); a one-cell solid wall of height 0.4 in the first
     column right of x = 3.5; dry (gas) right of it.  Hydrostatic density below each column's
     free surface (the detector's value), k0 = 6.54e5, at rest.  The profile values are kept in
-    meta["theta"]."""
+    meta["theta"]; ``theta`` given replaces the seeded ones (gradient checks)."""
     rng = np.random.default_rng(seed)
-    theta = 0.6 + 0.1 * rng.uniform(-1.0, 1.0, n_theta)
+    theta = 0.6 + 0.1 * rng.uniform(-1.0, 1.0, n_theta) if theta is None else np.asarray(theta, float)
+    n_theta = theta.size
     s = Scenario("wall_impact", nx, ny, 0.0, 4.0, 0.0, 2.0, k0=6.54e5, steps=400,
                  meta={"seed": seed, "theta": theta.tolist()})
     xc = s.xc()
@@ -285,6 +286,52 @@ def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64):
     q[:, solid == 1] = gas[:, None]
     s.q = q
     return s
+
+
+def wall_impact_theta_vjp(s: Scenario, lam0) -> np.ndarray:
+    """dJ/dtheta from dJ/dq0 (``lam0``, [4, ny, nx]) for a ``wall_impact`` state: the chain rule
+    through its construction, with the same switches held fixed as it takes them (which cells the
+    surface cuts, which cells are liquid).  h(x_i) = sum_k L_k(x_i) theta_k with the hat functions
+    of the linear interpolation; in a column, d frac/dh = 1/dy in the cut cell, the surface height
+    moves with h one for one, alpha = a_g + frac (a_l - a_g), and the liquid density
+    rho0 exp(-a (y - y_surf)) moves by a rho per unit of surface height."""
+    lam0 = np.asarray(lam0, dtype=float)
+    theta = np.asarray(s.meta["theta"], dtype=float)
+    n_theta = theta.size
+    xk = 3.5 * np.arange(n_theta) / (n_theta - 1)
+    xc, yc = s.xc(), s.yc()
+    ybot = s.y0 + np.arange(s.ny) * s.dy
+    a = s.g * s.rho0 / s.k0
+    alpha, q0 = s.q[3], s.q[0]
+    rho = q0 / alpha
+    solid = s.solid if s.solid is not None else np.zeros((s.ny, s.nx), np.uint8)
+    dJdh = np.zeros(s.nx)
+    for i in range(s.nx):
+        if xc[i] >= 3.5:
+            continue
+        h = float(np.interp(xc[i], xk, theta))
+        z = (h - ybot) / s.dy
+        cut = (z > 0.0) & (z < 1.0) & (solid[:, i] == 0)
+        dfrac = np.where(cut, 1.0 / s.dy, 0.0)
+        dalpha = dfrac * (s.alpha_liq - s.alpha_gas)
+        col_f = solid[:, i] == 0
+        jb = int(np.argmax(col_f)) if col_f.any() else s.ny
+        y_surf = (s.y0 + jb * s.dy) + s.dy * float(np.clip(z[col_f], 0.0, 1.0).sum())
+        dysurf = s.dy * float(dfrac.sum())
+        liq = col_f & (yc < y_surf)
+        drho = np.where(liq, a * rho[:, i] * dysurf, 0.0)
+        dq0 = rho[:, i] * dalpha + alpha[:, i] * drho
+        dJdh[i] = float(lam0[0, :, i] @ dq0 + lam0[3, :, i] @ dalpha)
+    # h_i = sum_k L_k(x_i) theta_k: the transpose of the interpolation
+    grad = np.zeros(n_theta)
+    for i in range(s.nx):
+        if xc[i] >= 3.5 or dJdh[i] == 0.0:
+            continue
+        k = min(int(np.searchsorted(xk, xc[i], side="right")) - 1, n_theta - 2)
+        w1 = (xc[i] - xk[k]) / (xk[k + 1] - xk[k])
+        grad[k] += (1.0 - w1) * dJdh[i]
+        grad[k + 1] += w1 * dJdh[i]
+    return grad
 
 
 # ---------------------------------------------------------------------------------------------
@@ -380,6 +427,30 @@ def smooth_state(s: Scenario, amp: float = 1e-3, vel: float = 0.05) -> Scenario:
     out = s.copy()
     out.q = q
     out.name = s.name + "_smooth"
+    return out
+
+
+def smooth_state_vjp(s: Scenario, lam, amp: float = 1e-3, vel: float = 0.05) -> np.ndarray:
+    """dJ/d(s.q) from dJ/d(smooth_state(s).q): the transpose of smooth_state's Jacobian, with its
+    liquid/gas split held fixed.  Liquid: alpha' = f alpha, (alpha rho)' = f w alpha rho and the
+    momenta (alpha rho)' times the (fixed) velocity field; gas: momenta alpha rho times vel."""
+    lam = np.asarray(lam, dtype=float)
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    q = s.q
+    fl = s.fluid()
+    liq = fl & (q[3] > 0.5)
+    gas = fl & ~liq
+    frac = 1.0 - 0.1 * amp * (1.0 + np.sin(2 * np.pi * X / 0.31 + 1.1) * np.sin(2 * np.pi * Y / 0.19 + 0.4))
+    wave = np.sin(2 * np.pi * X / 0.37 + 0.3) * np.sin(2 * np.pi * Y / 0.23 + 0.7)
+    u = np.where(liq, vel * (1.0 + 0.5 * np.sin(2 * np.pi * (X + Y) / 0.41)), np.where(gas, vel, 0.0))
+    v = np.where(liq, vel * (1.0 + 0.5 * np.cos(2 * np.pi * (X - Y) / 0.29)), np.where(gas, vel, 0.0))
+    dar = np.where(liq, frac * (1.0 + amp * wave), 1.0)  # d(alpha rho)'/d(alpha rho)
+    out = lam.copy()
+    lam_ar = lam[0] + np.where(fl, lam[1] * u + lam[2] * v, 0.0)
+    out[0] = np.where(fl, lam_ar * dar, lam[0])
+    out[1] = np.where(fl, 0.0, lam[1])
+    out[2] = np.where(fl, 0.0, lam[2])
+    out[3] = np.where(liq, lam[3] * frac, lam[3])
     return out
 
 

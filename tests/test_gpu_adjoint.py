@@ -161,3 +161,121 @@ def test_autograd_step_function_uses_the_adjoint(bn, torch_cuda):
         (out * w).sum().backward()
         direct = sim.adjoint_step(torch.from_numpy(s.q).cuda(), w.contiguous(), 1e-4)
     assert torch.equal(q.grad, direct)
+
+
+def test_checkpointed_trajectory_gradient(bn, torch_cuda):
+    """bn2d.trajectory_gradient (checkpoints every `segment` steps, recomputation, reverse sweep) is
+    bitwise the reverse sweep over every stored state (the forward step does not depend on how its
+    launch is scheduled, so recomputed states are the original ones), its loss is the plain sum, and
+    along a smooth direction from a smooth state it matches central differences of J.  (Directions
+    of cell-to-cell noise move alpha across the limiter's min/max selections of this state's small
+    alpha fluctuations: the quotients then disagree between h and h/2 by up to 25 % even for one
+    step, while for this smooth direction over 10 steps they agree to 3e-9.)"""
+    torch = torch_cuda
+    s = sc.smooth_state(sc.wall_impact(0, nx=48, ny=24))
+    rng = np.random.default_rng(3)
+    q0 = torch.from_numpy(s.q).cuda()
+    w = torch.from_numpy(rng.standard_normal(s.q.shape) * s.fluid()).cuda()
+    with bn.Simulation(s) as sim:
+        sim.set_state(q0)
+        dt = sim.compute_dt()
+        N = 23
+        J, g = bn.trajectory_gradient(sim, q0, dt, N, w, segment=5, with_loss=True)
+        g_plain = bn.trajectory_gradient(sim, q0, dt, N, w, segment=7)
+        states, J_ref = [q0.clone()], 0.0
+        sim.set_state(q0)
+        for _ in range(N):
+            sim.step(dt)
+            q = sim.get_state()
+            J_ref += float((w * q).sum())
+            states.append(q)
+        lam = torch.zeros_like(q0)
+        for n in range(N - 1, -1, -1):
+            lam = sim.adjoint_step(states[n], lam + w, dt)
+        assert torch.equal(g, lam) and torch.equal(g_plain, lam)
+        assert J == pytest.approx(J_ref, rel=1e-13)
+
+        N = 10
+        g = bn.trajectory_gradient(sim, q0, dt, N, w, segment=3)
+
+        def loss(qi):
+            sim.set_state(qi)
+            tot = torch.zeros((), dtype=torch.float64, device="cuda")
+            for _ in range(N):
+                sim.step(dt)
+                tot += (w * sim.get_state()).sum()
+            return float(tot)
+
+        scale = np.stack([np.abs(s.q[0])] * 3 + [np.abs(s.q[3])]) * s.fluid()
+        X, Y = np.meshgrid(s.xc(), s.yc())
+        d = torch.from_numpy(np.stack([np.sin(3 * X + Y + k) for k in range(4)]) * scale).cuda()
+        h = 1e-7
+        fd1 = (loss(q0 + h * d) - loss(q0 - h * d)) / (2 * h)
+        fd2 = (loss(q0 + h / 2 * d) - loss(q0 - h / 2 * d)) / h
+        ad = float((g * d).sum())
+        spread = abs(fd1 - fd2) / abs(fd2)
+        print(f"trajectory: adjoint {ad:.12e} fd {fd2:.12e} rel {abs(ad - fd2) / abs(fd2):.2e} "
+              f"fd h vs h/2 {spread:.2e}", flush=True)
+        assert spread < 1e-6
+        assert abs(ad - fd2) <= TOL * abs(fd2)
+
+
+def test_trajectory_gradient_of_no_steps_is_zero(bn, torch_cuda):
+    s = sc.wall_impact(0, nx=16, ny=8)
+    q0 = torch_cuda.from_numpy(s.q).cuda()
+    with bn.Simulation(s) as sim:
+        sim.set_state(q0)
+        g = bn.trajectory_gradient(sim, q0, sim.compute_dt(), 0, torch_cuda.ones_like(q0))
+    assert float(g.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("kind", ["initial", "smooth"])
+def test_profile_gradient_matches_differences(bn, torch_cuda, kind):
+    """dJ/dtheta for the 64 free-surface profile values of the 512 x 256 wall-impact workload: the
+    checkpointed adjoint gradient chained through the state's construction
+    (scenarios.wall_impact_theta_vjp, and smooth_state_vjp for the smooth variant) against central
+    differences of J over 40 steps of the workload's loss, along two seeded directions.  Over this
+    horizon J is smooth in theta (the quotients at h and h/2 agree to about 1e-7); over the
+    workload's full 400 steps the impact wave's limiter switches dominate the quotients."""
+    torch = torch_cuda
+    s = sc.wall_impact(0)
+    iw = s.meta["wall_column"] - 1
+    theta0 = np.asarray(s.meta["theta"])
+
+    def state(theta):
+        st = sc.wall_impact(0, theta=theta)
+        return torch.from_numpy((sc.smooth_state(st) if kind == "smooth" else st).q).cuda()
+
+    N = 40
+    with bn.Simulation(s) as sim:
+        q0 = state(theta0)
+        sim.set_state(torch.from_numpy(s.q).cuda())
+        dt = sim.compute_dt()
+        w = torch.zeros_like(q0)
+        w[0, :, iw] = dt * s.dy * s.k0 / s.rho0
+        w[3, :, iw] = -dt * s.dy * s.k0
+        w *= torch.from_numpy(s.fluid()).cuda()
+        g = bn.trajectory_gradient(sim, q0, dt, N, w, segment=20).cpu().numpy()
+        if kind == "smooth":
+            g = sc.smooth_state_vjp(s, g)
+        gth = sc.wall_impact_theta_vjp(s, g)
+
+        def loss(theta):
+            sim.set_state(state(theta))
+            tot = torch.zeros((), dtype=torch.float64, device="cuda")
+            for _ in range(N):
+                sim.step(dt)
+                tot += (w * sim.get_state()).sum()
+            return float(tot)
+
+        rng = np.random.default_rng(11)
+        for _ in range(2):
+            d = rng.normal(size=theta0.size)
+            h = 1e-7
+            fd1 = (loss(theta0 + h * d) - loss(theta0 - h * d)) / (2 * h)
+            fd2 = (loss(theta0 + h / 2 * d) - loss(theta0 - h / 2 * d)) / h
+            ad = float(gth @ d)
+            spread = abs(fd1 - fd2) / abs(fd2)
+            print(f"theta ({kind}): adjoint {ad:.10e} fd {fd2:.10e} rel {abs(ad - fd2) / abs(fd2):.2e} "
+                  f"fd h vs h/2 {spread:.2e}", flush=True)
+            assert abs(ad - fd2) <= (TOL + 2 * spread) * abs(fd2)
