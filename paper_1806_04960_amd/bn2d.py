@@ -328,31 +328,29 @@ def step_function():
     return StepFn
 
 
-def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False):
-    """Gradient of J = sum_{n=1..N} <weights, Q^n> over N steps of fixed length dt from q0 with
-    respect to q0, by the discrete adjoint (``bn_adjoint_step``): the forward run keeps the state
-    every ``segment`` steps, then each segment, last first, is recomputed from its checkpoint and
-    reversed step by step.  Memory: N/segment + segment states.  Returns dJ/dq0, or (J, dJ/dq0) with
-    ``with_loss`` (J then also costs a reduction per forward step).  Leaves the context at the start
-    of the first segment."""
+def _trajectory_forward(sim, q0, dt: float, N: int, w, seg: int, with_loss: bool):
+    """N steps of length dt from q0: the loss sum_n <w, Q^n> (if asked) and the checkpoints."""
     import torch
 
-    N, seg = int(n_steps), int(segment)
-    if N < 0 or seg < 1:
-        raise ValueError("n_steps >= 0 and segment >= 1 required")
-    w = weights.contiguous()
     ck = [q0.detach().clone()]
     sim.set_state(ck[0])
     J = torch.zeros((), dtype=torch.float64, device=q0.device)
     for k in range(N):
         sim.step(dt)
-        last = k + 1 == N
-        if with_loss or ((k + 1) % seg == 0 and not last):
+        keep = (k + 1) % seg == 0 and k + 1 < N
+        if with_loss or keep:
             q = sim.get_state()
             if with_loss:
                 J += (w * q).sum()
-            if (k + 1) % seg == 0 and not last:
+            if keep:
                 ck.append(q)
+    return J, ck
+
+
+def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int):
+    """dJ/dq0 from the checkpoints: each segment, last first, recomputed and reversed."""
+    import torch
+
     lam = torch.zeros_like(ck[0])
     buf = [None] * seg
     for c in range(len(ck) - 1, -1, -1):
@@ -367,7 +365,52 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
             lam = lam + w  # dJ/dQ^{n0+k+1}
             lam = sim.adjoint_step(buf[k], lam, dt)
     sim.set_state(ck[0])
+    return lam
+
+
+def _check_trajectory(N, seg):
+    if int(N) < 0 or int(seg) < 1:
+        raise ValueError("n_steps >= 0 and segment >= 1 required")
+    return int(N), int(seg)
+
+
+def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False):
+    """Gradient of J = sum_{n=1..N} <weights, Q^n> over N steps of fixed length dt from q0 with
+    respect to q0, by the discrete adjoint (``bn_adjoint_step``): the forward run keeps the state
+    every ``segment`` steps, then each segment, last first, is recomputed from its checkpoint and
+    reversed step by step.  Memory: N/segment + segment states.  Returns dJ/dq0, or (J, dJ/dq0) with
+    ``with_loss`` (J then also costs a reduction per forward step).  Leaves the context at q0 (its
+    elapsed time restarted)."""
+    N, seg = _check_trajectory(n_steps, segment)
+    w = weights.contiguous()
+    J, ck = _trajectory_forward(sim, q0, float(dt), N, w, seg, with_loss)
+    lam = _trajectory_reverse(sim, ck, float(dt), N, w, seg)
     return (float(J), lam) if with_loss else lam
+
+
+def trajectory_loss_function():
+    """A ``torch.autograd.Function`` for the same loss: ``TrajLoss.apply(sim, q0, dt, n_steps,
+    weights, segment)`` returns J = sum_{n=1..N} <weights, Q^n> (a 0-dim tensor) from a forward run
+    that keeps the checkpoints; its backward recomputes each segment and runs the discrete adjoint
+    (the gradient reaches q0 only; weights, dt and the model are constants)."""
+    import torch
+
+    class TrajLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sim, q0, dt, n_steps, weights, segment=20):
+            N, seg = _check_trajectory(n_steps, segment)
+            w = weights.detach().contiguous()
+            J, ck = _trajectory_forward(sim, q0.detach().contiguous(), float(dt), N, w, seg, True)
+            ctx.sim, ctx.dt, ctx.N, ctx.seg, ctx.w, ctx.ck = sim, float(dt), N, seg, w, ck
+            return J
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            lam = _trajectory_reverse(ctx.sim, ctx.ck, ctx.dt, ctx.N, ctx.w, ctx.seg)
+            ctx.ck = None
+            return None, grad_out * lam, None, None, None, None
+
+    return TrajLoss
 
 
 def tune_launch(obj, steps: int = 30, shapes=None):

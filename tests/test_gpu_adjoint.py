@@ -194,6 +194,11 @@ def test_checkpointed_trajectory_gradient(bn, torch_cuda):
             lam = sim.adjoint_step(states[n], lam + w, dt)
         assert torch.equal(g, lam) and torch.equal(g_plain, lam)
         assert J == pytest.approx(J_ref, rel=1e-13)
+        # the same through torch.autograd
+        q_leaf = q0.clone().requires_grad_(True)
+        J_t = bn.trajectory_loss_function().apply(sim, q_leaf, dt, N, w, 5)
+        (2.0 * J_t).backward()
+        assert float(J_t.detach()) == J and torch.equal(q_leaf.grad, 2.0 * lam)
 
         N = 10
         g = bn.trajectory_gradient(sim, q0, dt, N, w, segment=3)
