@@ -57,6 +57,13 @@ __device__ __forceinline__ const Member &member_at(unsigned long long base, int 
     asm volatile("" : "+s"(addr));
     return *(const Member *)(MemberPtr)addr;
 }
+// The same for a member whose record address was computed once (a march keeps it instead of the
+// array base and the index: two scalar registers fewer to spill and restore in its row loop).
+__device__ __forceinline__ const Member &member_ref(unsigned long long addr)
+{
+    asm volatile("" : "+s"(addr));
+    return *(const Member *)(MemberPtr)addr;
+}
 __device__ __forceinline__ const Control &control_at(unsigned long long addr)
 {
     asm volatile("" : "+s"(addr));
@@ -233,12 +240,13 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
                       int (*sf)[64], int b, int g, int strip, int j0, int E, int slot)
 {
     const int lane = threadIdx.x;
+    const unsigned long long mab = ma + (unsigned long long)__builtin_amdgcn_readfirstlane(b) * sizeof(Member);
     int nx, ny;
     const double *Qp;
     double *Qnp;
     const uint8_t *solid;
     {
-        const Member &M = member_at(ma, b);
+        const Member &M = member_ref(mab);
         nx = M.K.nx;
         ny = M.K.ny;
         Qp = M.q[a.cur];
@@ -248,7 +256,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     const double dt = member_dt(a, ma, b);
     double dtdx, dtdy;
     {
-        const Consts &K = member_at(ma, b).K;
+        const Consts &K = member_ref(mab).K;
         dtdx = dt * K.inv_dx;
         dtdy = dt * K.inv_dy;
     }
@@ -261,7 +269,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     const size_t plane = (size_t)nx * ny;
     double y0c = 0.0;
     if (colin) {
-        const Member &M = member_at(ma, b);
+        const Member &M = member_ref(mab);
         y0c = (M.K.ylo + M.jb[i] * M.K.dy) + M.K.dy * ((double)M.S[a.m3][i] * M.fix_inv);
     }
     unsigned long long *desc = slot >= 0 ? control_at(ca).desc + slot : nullptr;
@@ -292,7 +300,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
             const double v = Qp[k * plane + cidx];
             lq[k] = in ? v : dflt[k];
         }
-        lf = cell_flags(i, r, nx, ny, member_at(ma, b).K.bc, fluid);
+        lf = cell_flags(i, r, nx, ny, member_ref(mab).K.bc, fluid);
     };
     load_row(j0 - 2);
 
@@ -329,7 +337,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         const bool fl = rec_lane && (fc_mid & F_FLUID);
         Rec rc;
         if (fl) {
-            const Consts &K = member_at(ma, b).K;
+            const Consts &K = member_ref(mab).K;
             LdsStencil st{sq, sf, {s_lo, s_mid, s_hi}, lane};
             reconstruct(K, st, jr, y0c, dt, rc);
         } else {
@@ -348,7 +356,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         // cell is not needed compute on benign copies and discard the result. -----------------
         double X[4] = {0, 0, 0, 0};
         if (jr_inside) {
-            const Consts &K = member_at(ma, b).K;
+            const Consts &K = member_ref(mab).K;
             double qWr[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) qWr[k] = shfl_from_right(rc.qW[k]);
@@ -374,7 +382,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         // ---- y-edge between row jr-1 (pending north state) and row jr ----------------------
         double DyM[4] = {0, 0, 0, 0}, DyP[4] = {0, 0, 0, 0};
         if (r > j0) {
-            const Consts &K = member_at(ma, b).K;
+            const Consts &K = member_ref(mab).K;
             const bool bf = rec_lane && (nF & F_FLUID);
             double qm[4], qp[4];
 #pragma unroll
@@ -392,7 +400,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         // ---- finish row jr-1 ---------------------------------------------------------------
         const int jf = jr - 1;
         if (jf >= j0 && jf < ny && out_lane) {
-            const Member &M = member_at(ma, b);
+            const Member &M = member_ref(mab);
             const Consts &K = M.K;
             const size_t cidx = (size_t)jf * nx + i;
             const bool fluid = sf[s_lo][lane] & F_FLUID;  // solid cells keep their values
@@ -426,7 +434,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         nF = fc_mid;
     }
     {
-        const Member &M = member_at(ma, b);
+        const Member &M = member_ref(mab);
         const int m_next = a.m3 == 2 ? 0 : a.m3 + 1;
         if (out_lane && colfix != 0) atomicAdd((unsigned long long *)&M.S[m_next][i], (unsigned long long)colfix);
 #pragma unroll
@@ -442,7 +450,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
 
     // recorded cost of the rows marched here, for the next step's partition
     const Control &C = control_at(ca);
-    const long long cbase = member_at(ma, b).cost0 + (long long)strip * ny;  // (the strip's cost_base)
+    const long long cbase = member_ref(mab).cost0 + (long long)strip * ny;  // (the strip's cost_base)
     const double spent = (double)(clock64() - t_begin);
     const float per_row = (float)(spent / (E - j0));
     for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[cbase + rr] = per_row;
