@@ -368,9 +368,16 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int):
     return lam
 
 
-def _check_trajectory(N, seg):
+def _check_trajectory(N, seg, q0, weights):
+    import torch
+
     if int(N) < 0 or int(seg) < 1:
         raise ValueError("n_steps >= 0 and segment >= 1 required")
+    for name, t in (("q0", q0), ("weights", weights)):
+        if t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError(f"{name} must be a float64 CUDA tensor")
+    if weights.shape != q0.shape:
+        raise ValueError("weights must have the shape of the state")
     return int(N), int(seg)
 
 
@@ -381,7 +388,7 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
     reversed step by step.  Memory: N/segment + segment states.  Returns dJ/dq0, or (J, dJ/dq0) with
     ``with_loss`` (J then also costs a reduction per forward step).  Leaves the context at q0 (its
     elapsed time restarted)."""
-    N, seg = _check_trajectory(n_steps, segment)
+    N, seg = _check_trajectory(n_steps, segment, q0, weights)
     w = weights.contiguous()
     J, ck = _trajectory_forward(sim, q0, float(dt), N, w, seg, with_loss)
     lam = _trajectory_reverse(sim, ck, float(dt), N, w, seg)
@@ -398,7 +405,7 @@ def trajectory_loss_function():
     class TrajLoss(torch.autograd.Function):
         @staticmethod
         def forward(ctx, sim, q0, dt, n_steps, weights, segment=20):
-            N, seg = _check_trajectory(n_steps, segment)
+            N, seg = _check_trajectory(n_steps, segment, q0, weights)
             w = weights.detach().contiguous()
             J, ck = _trajectory_forward(sim, q0.detach().contiguous(), float(dt), N, w, seg, True)
             ctx.sim, ctx.dt, ctx.N, ctx.seg, ctx.w, ctx.ck = sim, float(dt), N, seg, w, ck

@@ -144,3 +144,14 @@ def test_batch_create_rejects_too_many_strips_in_total():
     a.nx = 0x7FFF * 60
     rc, out = _batch_create([a, sc.uniform_tank(4, 4)])
     assert rc == bn2d.BN_EINVAL and not out.value
+
+
+def test_trajectory_gradient_rejects_bad_arguments():
+    import torch
+    q = torch.zeros((4, 2, 2), dtype=torch.float64)
+    with pytest.raises(ValueError, match="n_steps"):
+        bn2d.trajectory_gradient(None, q, 1.0, -1, q)
+    with pytest.raises(ValueError, match="segment"):
+        bn2d.trajectory_gradient(None, q, 1.0, 3, q, segment=0)
+    with pytest.raises(ValueError, match="CUDA"):
+        bn2d.trajectory_gradient(None, q, 1.0, 3, q)
