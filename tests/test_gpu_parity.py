@@ -264,3 +264,22 @@ def test_tallest_grid(oracle, bn, torch_cuda):
                                                                       MAX_ROWS // 2 + np.arange(-3, 3)])
     cells = np.concatenate([rows * 2, rows * 2 + 1])
     _one_step_on_sampled_cells(oracle, bn, torch_cuda, s, cells, 14)
+
+
+def test_fully_solid_columns_and_a_solid_strip_edge(oracle, bn, torch_cuda):
+    """Columns that are solid from bottom to top (no fluid cell, free surface at the top of the
+    grid), one of them on a strip seam (columns 59 and 60), a solid step at the west wall, and a
+    fully solid last column: the fluid cells beside them follow the oracle and the solid cells keep
+    their values."""
+    s = sc.dam_break_small(97, 41)
+    solid = np.zeros((s.ny, s.nx), np.uint8)
+    solid[:, [13, 59, 60, s.nx - 1]] = 1
+    solid[:9, 0:3] = 1
+    s.solid = solid
+    s.q[:, solid == 1] = np.array([s.alpha_gas * s.rho0, 0.0, 0.0, s.alpha_gas])[:, None]
+    s = sc.random_state(s, seed=21, amp=0.002, vel=0.02)
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 60)
+    qo, to, dto = oracle.run(s, s.q, 60)
+    assert_parity(s, qg, qo)
+    assert np.array_equal(qg[:, solid == 1], s.q[:, solid == 1])
+    assert abs(tg - to) <= 1e-12 * to
