@@ -10,9 +10,10 @@
 //   Q^{n+1}_c   = Q^n_c - dt/dx (D+_W + D-_E + fdiff) - dt/dy (D+_S + D-_N + gdiff) - dt vol
 // is reversed in five passes, one thread per cell or edge, through library-owned planes:
 //   1. adj_rec_kernel     recompute Rec_c (the edge states the edges need), 21 planes
-//   2. adj_xedge_kernel,  per edge: recompute D-+, reverse it with the adjoints of the two cells'
-//      adj_yedge_kernel   updates, and write the adjoints of the edge states to their owners
-//                         (each edge state feeds exactly one edge: no accumulation), 18 planes
+//   2. adj_edge_kernel    per x- and y-edge (one launch for both kinds): recompute D-+, reverse
+//                         it with the adjoints of the two cells' updates, and write the adjoints
+//                         of the edge states to their owners (each edge state feeds exactly one
+//                         edge: no accumulation), 18 planes
 //   3. adj_cell_kernel    reverse the reconstruction: adjoints of the 3 x 3 stencil (36 planes)
 //                         and of y0_i (1 plane)
 //   4. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
@@ -123,11 +124,10 @@ __global__ __launch_bounds__(256) void adj_rec_kernel(AdjArgs a)
     a.rec[P_YN * n + c] = r.yN;
 }
 
-// x-edge e (between cells e-1 and e of row j), e = 0..nx.
-__global__ __launch_bounds__(64) void adj_xedge_kernel(AdjArgs a)
+// x-edge e (between cells e-1 and e of row j), e = 0..nx; t = j (nx+1) + e.
+__device__ __forceinline__ void adj_xedge(const AdjArgs &a, long long t)
 {
     const int ne = a.K.nx + 1;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)ne * a.K.ny) return;
     const int e = (int)(t % ne), j = (int)(t / ne);
     const int iL = e - 1, iR = e;
@@ -173,11 +173,10 @@ __global__ __launch_bounds__(64) void adj_xedge_kernel(AdjArgs a)
     }
 }
 
-// y-edge e (between rows e-1 and e of column i), e = 0..ny.
-__global__ __launch_bounds__(64) void adj_yedge_kernel(AdjArgs a)
+// y-edge e (between rows e-1 and e of column i), e = 0..ny; t = e nx + i.
+__device__ __forceinline__ void adj_yedge(const AdjArgs &a, long long t)
 {
     const int nx = a.K.nx;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)nx * (a.K.ny + 1)) return;
     const int i = (int)(t % nx), e = (int)(t / nx);
     const int jB = e - 1, jT = e;
@@ -226,6 +225,17 @@ __global__ __launch_bounds__(64) void adj_yedge_kernel(AdjArgs a)
         for (int k = 0; k < 4; ++k) a.fb[(P_QS + k) * n + cT] = qpb[k] + (flB ? 0.0 : qmb[k]);
         a.fb[P_E1S * n + cT] = e1pb + (flB ? 0.0 : e1mb);
     }
+}
+
+// Both edge passes in one launch (they read the same reconstruction planes and write disjoint
+// adjoint planes): the first nbx workgroups take the x-edges, the rest the y-edges, so that the two
+// halves fill the GPU together instead of one after the other.
+__global__ __launch_bounds__(64) void adj_edge_kernel(AdjArgs a, unsigned nbx)
+{
+    if (blockIdx.x < nbx)
+        adj_xedge(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+    else
+        adj_yedge(a, (long long)(blockIdx.x - nbx) * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
@@ -354,8 +364,8 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     const unsigned gc = (unsigned)((n + 255) / 256), gc64 = (unsigned)((n + 63) / 64);
     hipLaunchKernelGGL(bn::adj_rec_kernel, dim3(gc), dim3(256), 0, stream, a);
     const size_t nxe = (size_t)(K.nx + 1) * K.ny, nye = (size_t)K.nx * (K.ny + 1);
-    hipLaunchKernelGGL(bn::adj_xedge_kernel, dim3((unsigned)((nxe + 63) / 64)), dim3(64), 0, stream, a);
-    hipLaunchKernelGGL(bn::adj_yedge_kernel, dim3((unsigned)((nye + 63) / 64)), dim3(64), 0, stream, a);
+    const unsigned nbx = (unsigned)((nxe + 63) / 64), nby = (unsigned)((nye + 63) / 64);
+    hipLaunchKernelGGL(bn::adj_edge_kernel, dim3(nbx + nby), dim3(64), 0, stream, a, nbx);
     hipLaunchKernelGGL(bn::adj_cell_kernel, dim3(gc64), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
                        0, stream, a);
