@@ -252,6 +252,17 @@ def adjoint_main(args):
     b.record()
     torch.cuda.synchronize()
     grad_ms = a.elapsed_time(b) / reps
+    # the same gradient keeping all N states in HBM (no recomputation)
+    bn2d.trajectory_gradient(sim, q0, dt, N, w, store_all=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        g_all = bn2d.trajectory_gradient(sim, q0, dt, N, w, store_all=True)
+    b.record()
+    torch.cuda.synchronize()
+    grad_all_ms = a.elapsed_time(b) / reps
+    assert torch.equal(g_all, g)
+    del g_all
     # the adjoint step alone
     lam = torch.randn((4, s.ny, s.nx), dtype=torch.float64, device="cuda")
     out = torch.empty_like(lam)
@@ -268,7 +279,8 @@ def adjoint_main(args):
     b.record()
     torch.cuda.synchronize()
     step_ms = a.elapsed_time(b) / 100
-    print(f"# forward {fwd_ms:.2f} ms, gradient {grad_ms:.2f} ms (x{grad_ms / fwd_ms:.2f}); step {step_ms*1e3:.1f} us, "
+    print(f"# forward {fwd_ms:.2f} ms, gradient {grad_ms:.2f} ms (x{grad_ms / fwd_ms:.2f}), all states kept "
+          f"{grad_all_ms:.2f} ms (x{grad_all_ms / fwd_ms:.2f}); step {step_ms*1e3:.1f} us, "
           f"adjoint step {adj_ms*1e3:.1f} us", file=sys.stderr, flush=True)
 
     # gradient checks: dJ/dq0 along seeded patch directions of the initial state, and dJ/dtheta
@@ -361,6 +373,7 @@ def adjoint_main(args):
         "config": {"workload": f"discrete adjoint, wall impact {s.nx}x{s.ny} seed 0, {N} steps of fixed dt, "
                                f"checkpoints every {seg}", "nx": s.nx, "ny": s.ny},
         "adjoint": {"forward_ms": fwd_ms, "gradient_ms": grad_ms, "cost_ratio": grad_ms / fwd_ms,
+                    "gradient_all_states_ms": grad_all_ms, "cost_ratio_all_states": grad_all_ms / fwd_ms,
                     "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3,
                     "grad_theta_norm": float(np.linalg.norm(gth_of["initial"])), "fd_checks": checks,
                     "fd_checks_theta_40_steps": short},

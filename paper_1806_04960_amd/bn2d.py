@@ -381,17 +381,39 @@ def _check_trajectory(N, seg, q0, weights):
     return int(N), int(seg)
 
 
-def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False):
+def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False,
+                        store_all: bool = False):
     """Gradient of J = sum_{n=1..N} <weights, Q^n> over N steps of fixed length dt from q0 with
     respect to q0, by the discrete adjoint (``bn_adjoint_step``): the forward run keeps the state
     every ``segment`` steps, then each segment, last first, is recomputed from its checkpoint and
-    reversed step by step.  Memory: N/segment + segment states.  Returns dJ/dq0, or (J, dJ/dq0) with
-    ``with_loss`` (J then also costs a reduction per forward step).  Leaves the context at q0 (its
-    elapsed time restarted)."""
+    reversed step by step.  Memory: N/segment + segment states.  With ``store_all`` the forward run
+    keeps every state instead (N states, no recomputation: one forward step fewer per step where
+    device memory allows it).  Returns dJ/dq0, or (J, dJ/dq0) with ``with_loss`` (J then also costs a
+    reduction per forward step).  Leaves the context at q0 (its elapsed time restarted)."""
     N, seg = _check_trajectory(n_steps, segment, q0, weights)
     w = weights.contiguous()
-    J, ck = _trajectory_forward(sim, q0, float(dt), N, w, seg, with_loss)
-    lam = _trajectory_reverse(sim, ck, float(dt), N, w, seg)
+    dt = float(dt)
+    if store_all:
+        import torch
+
+        states = [q0.detach().clone()]
+        sim.set_state(states[0])
+        J = torch.zeros((), dtype=torch.float64, device=q0.device)
+        for k in range(N):
+            sim.step(dt)
+            if with_loss or k + 1 < N:
+                q = sim.get_state()
+                if with_loss:
+                    J += (w * q).sum()
+                if k + 1 < N:
+                    states.append(q)
+        lam = torch.zeros_like(states[0])
+        for n in range(N - 1, -1, -1):
+            lam = sim.adjoint_step(states[n], lam + w, dt)
+        sim.set_state(states[0])
+        return (float(J), lam) if with_loss else lam
+    J, ck = _trajectory_forward(sim, q0, dt, N, w, seg, with_loss)
+    lam = _trajectory_reverse(sim, ck, dt, N, w, seg)
     return (float(J), lam) if with_loss else lam
 
 

@@ -194,6 +194,8 @@ def test_checkpointed_trajectory_gradient(bn, torch_cuda):
             lam = sim.adjoint_step(states[n], lam + w, dt)
         assert torch.equal(g, lam) and torch.equal(g_plain, lam)
         assert J == pytest.approx(J_ref, rel=1e-13)
+        J_all, g_all = bn.trajectory_gradient(sim, q0, dt, N, w, with_loss=True, store_all=True)
+        assert torch.equal(g_all, lam) and J_all == J
         # the same through torch.autograd
         q_leaf = q0.clone().requires_grad_(True)
         J_t = bn.trajectory_loss_function().apply(sim, q_leaf, dt, N, w, 5)
