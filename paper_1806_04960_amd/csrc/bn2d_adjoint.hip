@@ -14,12 +14,14 @@
 //                         it with the adjoints of the two cells' updates, and write the adjoints
 //                         of the edge states to their owners (each edge state feeds exactly one
 //                         edge: no accumulation), 18 planes
-//   3. adj_cell_kernel    reverse the reconstruction: adjoints of the 3 x 3 stencil (36 planes)
-//                         and of y0_i (1 plane)
+//   3. adj_cell_kernel    reverse the reconstruction: adjoints of the 3 x 3 stencil (36 planes;
+//                         a first-order cell reaches only itself and writes only that entry and a
+//                         0 in the second-order flag plane) and of y0_i (1 plane)
 //   4. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
 //                         gather adds the blocks' partial sums in order: deterministic)
 //   5. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
-//                         fluid cells whose stencil holds c + the detector's dy/(alpha_l -
+//                         fluid cells whose stencil holds c (of a first-order neighbour only
+//                         c's own entry) + the detector's dy/(alpha_l -
 //                         alpha_g) times its column's y0 adjoint (alpha only); solid cells pass
 //                         lambda through (their state is copied and never read)
 #include <hip/hip_runtime.h>
@@ -41,8 +43,9 @@ struct AdjArgs {
     double dt, dtdx, dtdy;
     double *rec;            // kRecPlanes planes
     double *fb;             // kFacePlanes planes
-    double *wb;             // 36 planes
+    double *wb;             // 36 planes (a first-order cell writes only its own entry, (1, 1))
     double *y0b;            // 1 plane (0 for solid cells)
+    double *sob;            // 1 plane: 1 where the fluid cell's reconstruction is second order
     double *colb;           // [ceil(ny / kColRows)][nx] partial column sums
 };
 
@@ -251,6 +254,14 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
     double wq[3][3][4];
     int wf[3][3];
     load_stencil(a, i, j, wq, wf);
+    // the reconstruction's second-order switch (as reconstruct_rev takes it): a first-order cell's
+    // reverse reaches only the cell itself, so only that entry of its stencil adjoint is stored
+    bool so = wq[1][1][3] > a.K.so_thr;
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+        for (int di = 0; di < 3; ++di)
+            if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > a.K.so_thr)) so = false;
     RecBar rb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -274,12 +285,18 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
 #pragma unroll
             for (int k = 0; k < 4; ++k) wqb[dj][di][k] = 0.0;
     const double yb = reconstruct_rev(a.K, wq, wf, j, y0_of(a, i), a.dt, rb, wqb);
+    if (so) {
 #pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
+        for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
-        for (int di = 0; di < 3; ++di)
+            for (int di = 0; di < 3; ++di)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a.wb[((dj * 3 + di) * 4 + k) * n + c] = wqb[dj][di][k];
+                for (int k = 0; k < 4; ++k) a.wb[((dj * 3 + di) * 4 + k) * n + c] = wqb[dj][di][k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.wb[((1 * 3 + 1) * 4 + k) * n + c] = wqb[1][1][k];
+    }
+    a.sob[c] = so ? 1.0 : 0.0;
     a.y0b[c] = yb;
 }
 
@@ -316,6 +333,8 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
                 const int ii = i - di + 1, jj = j - dj + 1;
                 if (!fluid_at(a, ii, jj)) continue;
                 const size_t m = (size_t)jj * a.K.nx + ii;
+                // a first-order cell stored only its own entry
+                if (!(dj == 1 && di == 1) && !(a.sob[m] != 0.0)) continue;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) out[k] += a.wb[((dj * 3 + di) * 4 + k) * n + m];
             }
@@ -331,7 +350,7 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
 
 // Launch the five passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
 namespace bn {
-constexpr int kAdjPlanes = kRecPlanes + kFacePlanes + 36 + 1;
+constexpr int kAdjPlanes = kRecPlanes + kFacePlanes + 36 + 2;
 }
 
 size_t bn_adjoint_scratch(int nx, int ny)
@@ -360,7 +379,8 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.fb = a.rec + bn::kRecPlanes * n;
     a.wb = a.fb + bn::kFacePlanes * n;
     a.y0b = a.wb + 36 * n;
-    a.colb = a.y0b + n;
+    a.sob = a.y0b + n;
+    a.colb = a.sob + n;
     const unsigned gc = (unsigned)((n + 255) / 256), gc64 = (unsigned)((n + 63) / 64);
     hipLaunchKernelGGL(bn::adj_rec_kernel, dim3(gc), dim3(256), 0, stream, a);
     const size_t nxe = (size_t)(K.nx + 1) * K.ny, nye = (size_t)K.nx * (K.ny + 1);
