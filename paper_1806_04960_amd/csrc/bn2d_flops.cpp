@@ -167,7 +167,8 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
             }
             g_ops = 0;
             update_partial(qn, dpw, dme, rec[c].fdiff, rec[c].gdiff, rec[c].vol2, rec[c].vol3, dtv, dtdx, dtdy, P);
-            update_finish(P, dps, dmn, dtdy, q);
+            update_south(P, dps, dtdy, P);
+            update_finish(P, dmn, dtdy, q);
             c_upd += g_ops;
             g_ops = 0;
             (void)detector_term(K, q);

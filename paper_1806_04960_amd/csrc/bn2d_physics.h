@@ -411,10 +411,18 @@ BN_DEV void update_partial(const real_t Qn[4], const real_t DpW[4], const real_t
     X[3] = X[3] - dt * vol3;
 }
 
-BN_DEV void update_finish(const real_t X[4], const real_t DpS[4], const real_t DmN[4], real_t dtdy, real_t q[4])
+// The south edge's D+ applied to a partial update (when the row above is being solved), then the
+// north edge's D- (when that edge is known): what the cell's update is waiting for is 4 values.
+BN_DEV void update_south(const real_t X[4], const real_t DpS[4], real_t dtdy, real_t P[4])
 {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = X[k] - dtdy * (DpS[k] + DmN[k]);
+    for (int k = 0; k < 4; ++k) P[k] = X[k] - dtdy * DpS[k];
+}
+
+BN_DEV void update_finish(const real_t P[4], const real_t DmN[4], real_t dtdy, real_t q[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = P[k] - dtdy * DmN[k];
 }
 
 // Free-surface detector term of a fluid cell (Sec. 3.5) and its CFL rate (|u|+c)/dx + (|v|+c)/dy.

@@ -277,9 +277,9 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     const long long t_begin = clock64();
     unsigned long long claim = 0;
 
-    // pending row (below the row being reconstructed): its update without the y-edge terms, the
-    // D+ of its south edge, and its north edge state
-    double pX[4] = {0, 0, 0, 0}, pDpS[4] = {0, 0, 0, 0};
+    // pending row (below the row being reconstructed): its update with every term but its north
+    // edge's D-, and its north edge state
+    double pX[4] = {0, 0, 0, 0};
     double nQ[4] = {1, 0, 0, 1}, nE1 = 1.0, nAE = 1.0, nY = 0.0;
     int nF = 0;
     long long colfix = 0;
@@ -405,7 +405,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
             const size_t cidx = (size_t)jf * nx + i;
             const bool fluid = sf[s_lo][lane] & F_FLUID;  // solid cells keep their values
             double qn[4];
-            update_finish(pX, pDpS, DyM, dtdy, qn);
+            update_finish(pX, DyM, dtdy, qn);
 #pragma unroll
             for (int k = 0; k < 4; ++k) Qnp[k * plane + cidx] = fluid ? qn[k] : sq[s_lo][k][lane];
             const long long term = __double2ll_rn(detector_term(K, qn) * M.fix_scale);
@@ -419,11 +419,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         if (final_row) break;
 
         // ---- row jr becomes the pending row ------------------------------------------------
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            pX[k] = X[k];
-            pDpS[k] = DyP[k];
-        }
+        update_south(X, DyP, dtdy, pX);
         if (fl) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) nQ[k] = rc.qN[k];
