@@ -61,6 +61,16 @@
  *  [R19] Reflective wall: the ghost state is the interior edge state with its normal
  *        momentum negated (E-part and height copied); transmissive: a copy.  Solid cells
  *        are never updated.
+ *
+ * Literal forms (off by default; the test-suite builds them separately to show why [R12], [R14]
+ * and [R18] depart from the printed text):
+ *   -DBNREF_LITERAL_ROE_VELOCITY   b_4 velocity = the printed Roe average of u (v) with sqrt(rho)
+ *                                  weights between the end states of each (sub-)interval
+ *                                  (Sec. 3.2 and 3.3), instead of [R18];
+ *   -DBNREF_LITERAL_CELL_SWITCH    second order iff the cell's own alpha > 10 alpha_gas (Sec. 3.4),
+ *                                  instead of [R14];
+ *   -DBNREF_LITERAL_OWN_EQUILIBRIUM  each stencil neighbour's fluctuation taken against its own
+ *                                  equilibrium (its column's free surface), instead of [R12].
  */
 #include <math.h>
 #include <stdint.h>
@@ -99,6 +109,16 @@ typedef struct {
 static real eos_p(const model_t *m, real rho) { return m->k0 * (rho / m->rho0 - 1.0); }
 /* Sound speed squared, gamma k0/rho0 (rho/rho0)^(gamma-1) at gamma = 1 (Sec. 3). */
 static real eos_c2(const model_t *m) { return m->k0 / m->rho0; }
+
+#ifdef BNREF_LITERAL_ROE_VELOCITY
+/* Roe average of velocity component k (1: u, 2: v) between states a and b, weights sqrt(rho),
+ * rho = alpha rho / alpha (Sec. 3.2, 3.3 as printed). */
+static real roe_velocity(const real a[NV], const real b[NV], int k)
+{
+    real sa = sqrt(a[0] / a[3]), sb = sqrt(b[0] / b[3]);
+    return (sa * (a[k] / a[0]) + sb * (b[k] / b[0])) / (sa + sb);
+}
+#endif
 
 /* Conservative fluxes f and g of the augmented system (Sec. 2.1, general form).
  * The y-flux carries no pressure: d_y(alpha p) is a non-conservative term of B2. */
@@ -234,6 +254,9 @@ static void fluct_x(const model_t *m, const real qm[NV], const real qp[NV], real
             for (b = 0; b < NV; ++b) V[a][b] += w_gl[k] * Ak[a][b];
         ubar += w_gl[k] * (phi[1] / phi[0]);
     }
+#ifdef BNREF_LITERAL_ROE_VELOCITY
+    ubar = roe_velocity(qm, qp, 1);
+#endif
     for (k = 0; k < NV; ++k) Bdq[k] = 0.0;
     Bdq[3] = ubar * dq[3];
     for (a = 0; a < NV; ++a) {
@@ -305,9 +328,15 @@ static void fluct_y(const model_t *m, const real qm[NV], const real em[NV], cons
     }
     v14 = q14[2] / q14[0];
     v34 = q34[2] / q34[0];
+#ifdef BNREF_LITERAL_ROE_VELOCITY
+    residual_y(m, qm, em, q12, e12, roe_velocity(qm, q12, 2), R1);
+    residual_y(m, q12, e12, qp, ep, roe_velocity(q12, qp, 2), R2);
+    residual_y(m, qm, em, qp, ep, roe_velocity(qm, qp, 2), R3);
+#else
     residual_y(m, qm, em, q12, e12, v14, R1);
     residual_y(m, q12, e12, qp, ep, v34, R2);
     residual_y(m, qm, em, qp, ep, 0.5 * (v14 + v34), R3);
+#endif
     matrix_function(m, 1, 1, q14, S1);
     matrix_function(m, 1, 1, q34, S2);
     matrix_function(m, 1, 1, q12, S3);
@@ -411,10 +440,12 @@ static void reconstruct(const model_t *m, const double *Q, const real *Y0, int i
     estate(m, liquid, Y0[i], yc, r->ec);
     /* second order only where the cell and every fluid cell of its 3x3 stencil hold liquid [R14] */
     r->so = Qc[3] > 10.0 * m->ag;
+#ifndef BNREF_LITERAL_CELL_SWITCH
     for (dj = -1; dj <= 1; ++dj)
         for (di = -1; di <= 1; ++di)
             if (is_fluid(m, i + di, j + dj) && !(Q[3 * (size_t)m->nx * m->ny + (size_t)(j + dj) * m->nx + i + di] > 10.0 * m->ag))
                 r->so = 0;
+#endif
 
     yf[W] = yc; yf[E] = yc;
     if (r->so) { yf[S] = y_edge(m, j); yf[N] = y_edge(m, j + 1); }
@@ -437,7 +468,11 @@ static void reconstruct(const model_t *m, const double *Q, const real *Y0, int i
             if (is_fluid(m, ii, jj)) {
                 real qn[NV], en[NV];
                 load_q(m, Q, ii, jj, qn);
+#ifdef BNREF_LITERAL_OWN_EQUILIBRIUM
+                estate(m, qn[4] < Y0[ii], Y0[ii], qn[4], en);
+#else
                 estate(m, liquid, Y0[i], qn[4], en);
+#endif
                 for (k = 0; k < 4; ++k) phi[dj + 1][di + 1][k] = qn[k] - en[k];
             } else {
                 int out_x = (ii < 0 || ii >= m->nx), out_y = (jj < 0 || jj >= m->ny);

@@ -55,32 +55,64 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _bind(path):
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    dp = P(ctypes.c_double)
+    u8p = P(ctypes.c_uint8)
+    gp, pp = P(_Grid), P(_Params)
+    L.bnref_detector.argtypes = [gp, pp, u8p, dp, dp]
+    L.bnref_cfl.argtypes = [gp, pp, u8p, dp, dp, dp]
+    L.bnref_step.argtypes = [gp, pp, u8p, dp, ctypes.c_double, dp]
+    L.bnref_step_cells.argtypes = [gp, pp, u8p, dp, ctypes.c_double, ctypes.c_int64,
+                                   P(ctypes.c_int64), dp]
+    L.bnref_run.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, dp, dp]
+    L.bnref_flux.argtypes = [pp, ctypes.c_int32, dp, dp]
+    L.bnref_matrix.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, dp, dp]
+    L.bnref_fluct.argtypes = [pp, ctypes.c_int32, dp, dp, dp, dp, dp, dp]
+    L.bnref_reconstruct.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, dp, dp, dp, dp]
+    for name in ("bnref_detector", "bnref_cfl", "bnref_step", "bnref_step_cells", "bnref_run",
+                 "bnref_flux", "bnref_matrix", "bnref_fluct", "bnref_reconstruct"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
-        P = ctypes.POINTER
-        dp = P(ctypes.c_double)
-        u8p = P(ctypes.c_uint8)
-        gp, pp = P(_Grid), P(_Params)
-        L.bnref_detector.argtypes = [gp, pp, u8p, dp, dp]
-        L.bnref_cfl.argtypes = [gp, pp, u8p, dp, dp, dp]
-        L.bnref_step.argtypes = [gp, pp, u8p, dp, ctypes.c_double, dp]
-        L.bnref_step_cells.argtypes = [gp, pp, u8p, dp, ctypes.c_double, ctypes.c_int64,
-                                       P(ctypes.c_int64), dp]
-        L.bnref_run.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, dp, dp]
-        L.bnref_flux.argtypes = [pp, ctypes.c_int32, dp, dp]
-        L.bnref_matrix.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, dp, dp]
-        L.bnref_fluct.argtypes = [pp, ctypes.c_int32, dp, dp, dp, dp, dp, dp]
-        L.bnref_reconstruct.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, ctypes.c_int32,
-                                        ctypes.c_double, dp, dp, dp, dp]
-        for name in ("bnref_detector", "bnref_cfl", "bnref_step", "bnref_step_cells", "bnref_run",
-                     "bnref_flux", "bnref_matrix", "bnref_fluct", "bnref_reconstruct"):
-            getattr(L, name).restype = ctypes.c_int
-        _lib = L
+        _lib = _bind(LIB)
     return _lib
+
+
+# The literal forms of three passages that the oracle reads differently (compile-time switches of
+# bnref.c, off in the oracle itself); built on demand, for the tests that show why.
+VARIANTS = {
+    "roe_velocity": "BNREF_LITERAL_ROE_VELOCITY",
+    "cell_switch": "BNREF_LITERAL_CELL_SWITCH",
+    "own_equilibrium": "BNREF_LITERAL_OWN_EQUILIBRIUM",
+}
+
+
+class Variant:
+    """The oracle built with one literal-form switch: the same functions as this module."""
+
+    def __init__(self, name: str, out_dir: str):
+        path = os.path.join(out_dir, f"libbnref_{name}.so")
+        subprocess.check_call(["gcc", *CFLAGS, f"-D{VARIANTS[name]}", "-o", path, SRC, "-lm"])
+        self.name = name
+        self._L = _bind(path)
+
+    def step(self, s, q, dt):
+        return step(s, q, dt, L=self._L)
+
+    def run(self, s, q, n_steps):
+        return run(s, q, n_steps, L=self._L)
+
+    def cfl(self, s, q):
+        return cfl(s, q, L=self._L)
 
 
 def _dp(a):
@@ -124,21 +156,21 @@ def detector(s, q) -> np.ndarray:
     return y0
 
 
-def cfl(s, q):
+def cfl(s, q, L=None):
     """Return (lambda_max, dt)."""
     q = _state(s, q)
     keep, sp = _solid(s)
     lam, dt = ctypes.c_double(), ctypes.c_double()
-    _check(lib().bnref_cfl(_grid(s), params_struct(s), sp, _dp(q), ctypes.byref(lam), ctypes.byref(dt)),
+    _check((L or lib()).bnref_cfl(_grid(s), params_struct(s), sp, _dp(q), ctypes.byref(lam), ctypes.byref(dt)),
            "cfl")
     return lam.value, dt.value
 
 
-def step(s, q, dt: float) -> np.ndarray:
+def step(s, q, dt: float, L=None) -> np.ndarray:
     q = _state(s, q)
     keep, sp = _solid(s)
     out = np.empty_like(q)
-    _check(lib().bnref_step(_grid(s), params_struct(s), sp, _dp(q), float(dt), _dp(out)), "step")
+    _check((L or lib()).bnref_step(_grid(s), params_struct(s), sp, _dp(q), float(dt), _dp(out)), "step")
     return out
 
 
@@ -154,12 +186,12 @@ def step_cells(s, q, dt: float, cells) -> np.ndarray:
     return out
 
 
-def run(s, q, n_steps: int):
+def run(s, q, n_steps: int, L=None):
     """Advance ``n_steps`` CFL steps; returns (state, elapsed time, last dt)."""
     q = _state(s, q).copy()
     keep, sp = _solid(s)
     t, dt = ctypes.c_double(), ctypes.c_double()
-    _check(lib().bnref_run(_grid(s), params_struct(s), sp, _dp(q), int(n_steps), ctypes.byref(t),
+    _check((L or lib()).bnref_run(_grid(s), params_struct(s), sp, _dp(q), int(n_steps), ctypes.byref(t),
                            ctypes.byref(dt)), "run")
     return q, t.value, dt.value
 
