@@ -130,6 +130,19 @@ const char *bn_strerror(int code);
  * non-finite values. */
 int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev);
 
+/* bn_adjoint_step without any allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and errors as bn_adjoint_step (bitwise the same lambda: the same kernels), but the scratch is a
+ * fixed library array of 2^24 doubles (128 MiB) per GPU, reserved when the library's device code is
+ * loaded and held until the process ends, instead of memory allocated on the first call.  The grid
+ * must fit: 77 nx ny + nx (ceil(ny / 32) + 1) + 2 <= 2^24 (about 217 000 cells, e.g. 512 x 256 or
+ * 640 x 320), else BN_EINVAL before any work is enqueued.  The first call on a device resolves the
+ * array's address on that device (the current device must be the context's).  Every call on a GPU
+ * uses that GPU's one array: calls that overlap in time on one GPU (other streams, other contexts,
+ * other threads) race and give wrong results; calls ordered on one stream, or synchronised, do not.
+ * Calls no hipMalloc, hipFree or allocating library routine. */
+int bn_adjoint_step_noalloc(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev);
+
 /* ---- Batches: many grids advanced by one launch per step -------------------------------------
  * A batch holds `count` independent grids (members) of any sizes, parameters and masks, e.g. an
  * ensemble of scenarios too small to fill the device one by one.  Every bn_batch_run step advances

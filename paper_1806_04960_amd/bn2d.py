@@ -17,7 +17,7 @@ BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
            "bn_get_time", "bn_get_y0", "bn_status", "bn_set_launch", "bn_get_launch", "bn_destroy",
-           "bn_strerror", "bn_adjoint_step", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
+           "bn_strerror", "bn_adjoint_step", "bn_adjoint_step_noalloc", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
            "bn_batch_get_time", "bn_batch_get_y0", "bn_batch_status", "bn_batch_set_launch",
            "bn_batch_get_launch", "bn_batch_destroy")
 
@@ -65,6 +65,7 @@ def lib():
         L.bn_destroy.argtypes = [vp]
         L.bn_destroy.restype = None
         L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp]
+        L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp]
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
         i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
@@ -157,15 +158,23 @@ class Simulation:
     def adjoint_step(self, q, lam_next, dt: float, out=None):
         """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} for the step of length dt from state q
         (``bn_adjoint_step``).  q, lam_next: contiguous float64 CUDA tensors [4, ny, nx]."""
+        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out)
+
+    def adjoint_step_noalloc(self, q, lam_next, dt: float, out):
+        """The same adjoint through ``bn_adjoint_step_noalloc``: the library's fixed scratch array,
+        no allocation (the caller passes ``out``)."""
+        return self._adjoint(lib().bn_adjoint_step_noalloc, "bn_adjoint_step_noalloc", q, lam_next, dt, out)
+
+    def _adjoint(self, fn, name, q, lam_next, dt, out):
         import torch
         shape = (4, self.ny, self.nx)
-        for name, t in (("q", q), ("lam_next", lam_next)):
-            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
-                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
         if out is None:
             out = torch.empty(shape, dtype=torch.float64, device="cuda")
-        check(lib().bn_adjoint_step(self._ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(lam_next.data_ptr()),
-                                    float(dt), ctypes.c_void_p(out.data_ptr())), "bn_adjoint_step")
+        for arg, t in (("q", q), ("lam_next", lam_next), ("out", out)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError(f"{arg} must be a contiguous float64 CUDA tensor of shape {shape}")
+        check(fn(self._ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(lam_next.data_ptr()), float(dt),
+                 ctypes.c_void_p(out.data_ptr())), name)
         return out
 
     def time(self):

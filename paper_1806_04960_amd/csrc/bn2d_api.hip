@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -665,6 +666,65 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
                        g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
     HIP_TRY(hipGetLastError());
     HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, S, g.dev.fix_inv, dt, g.adj,
+                              b->stream));
+    return BN_OK;
+}
+
+}  // extern "C"
+
+// ---- the adjoint step without allocation ------------------------------------------------------
+// Scratch of bn_adjoint_step_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never names it in a launch or copy: its device address, per device, comes
+// from hipGetSymbolAddress on the first call on that device.
+namespace {
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 24;  // 128 MiB
+}
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;  // per device, null until resolved
+
+int scratch_address(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return hip_fail(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return BN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev)
+{
+    if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
+    bn_batch *b = c->b;
+    Grid &g = b->g[0];
+    const int nx = g.grid.nx, ny = g.grid.ny;
+    // the free-surface words (nx integrals, the CFL slot, the flag) follow the adjoint's planes
+    const size_t planes = bn_adjoint_scratch(nx, ny);
+    if (planes + (size_t)nx + 2 > kNoAllocScratchDoubles) return BN_EINVAL;
+    double *base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc) return rc;
+    long long *S = reinterpret_cast<long long *>(base + planes);
+    // the array keeps the previous call's contents: the integrals must start at zero
+    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 2 + 255) / 256), dim3(256), 0, b->stream, S, nx + 2);
+    HIP_TRY(hipGetLastError());
+    const int H = kReduceRows;
+    hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
+                       g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, S, g.dev.fix_inv, dt, base,
                               b->stream));
     return BN_OK;
 }
