@@ -8,7 +8,10 @@
  * or helper with the HIP library: it is written from the paper alone, plainly and slowly,
  * in FP64, in the paper's order and notation, so that a reader can check it by eye.
  *
- * Build:  gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -fPIC -shared -o libbnref.so bnref.c -lm
+ * Build:  gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -fopenmp -fPIC -shared -o libbnref.so bnref.c -lm
+ * (-fopenmp shares the rows of each sweep of a step out over threads: every cell is still
+ * computed by the same arithmetic, so results do not depend on the thread count; without it
+ * the same source builds a single-threaded oracle.)
  *
  * Where the paper is silent, ambiguous or garbled the oracle takes one reading; each reading
  * is tagged [Rn] where it is used and listed with its justification in the design notes.
@@ -83,6 +86,7 @@ typedef double real;
 #endif
 
 #define NV 5 /* (alpha rho, alpha rho u, alpha rho v, alpha, y) -- Sec. 2.1 */
+#define BNREF_PARALLEL_CELLS 65536 /* smaller grids run their sweeps on one thread */
 
 typedef struct { int32_t nx, ny; double x0, x1, y0, y1; } bnref_grid;
 typedef struct {
@@ -693,11 +697,15 @@ int bnref_step(const bnref_grid *gr, const bnref_params *pa, const uint8_t *soli
     rc = detector(&m, Qn, Y0);
     if (rc) goto done;
 
+    /* Rows are independent within each of the four sweeps below: with OpenMP they are shared
+     * out over threads, and every value is still computed by the same arithmetic. */
+#pragma omp parallel for private(i) schedule(dynamic, 1) if (plane >= BNREF_PARALLEL_CELLS)
     for (j = 0; j < m.ny; ++j)
         for (i = 0; i < m.nx; ++i)
             if (is_fluid(&m, i, j)) reconstruct(&m, Qn, Y0, i, j, dt, &R[(size_t)j * m.nx + i]);
 
     /* x-edges: edge fi sits between cells fi-1 and fi of row j. */
+#pragma omp parallel for private(i) schedule(dynamic, 1) if (plane >= BNREF_PARALLEL_CELLS)
     for (j = 0; j < m.ny; ++j)
         for (i = 0; i <= m.nx; ++i) {
             const recon_t *lf = is_fluid(&m, i - 1, j) ? &R[(size_t)j * m.nx + i - 1] : NULL;
@@ -706,6 +714,7 @@ int bnref_step(const bnref_grid *gr, const bnref_params *pa, const uint8_t *soli
             if (lf || rt) edge_x(&m, lf, rt, i == 0, i == m.nx, &Dxm[e], &Dxp[e]);
         }
     /* y-edges: edge fj sits between rows fj-1 and fj of column i. */
+#pragma omp parallel for private(i) schedule(dynamic, 1) if (plane >= BNREF_PARALLEL_CELLS)
     for (j = 0; j <= m.ny; ++j)
         for (i = 0; i < m.nx; ++i) {
             const recon_t *bt = is_fluid(&m, i, j - 1) ? &R[(size_t)(j - 1) * m.nx + i] : NULL;
@@ -714,6 +723,7 @@ int bnref_step(const bnref_grid *gr, const bnref_params *pa, const uint8_t *soli
             if (bt || tp) edge_y(&m, bt, tp, j == 0, j == m.ny, &Dym[e], &Dyp[e]);
         }
 
+#pragma omp parallel for private(i, k) schedule(dynamic, 1) if (plane >= BNREF_PARALLEL_CELLS)
     for (j = 0; j < m.ny; ++j)
         for (i = 0; i < m.nx; ++i) {
             size_t c = (size_t)j * m.nx + i;
@@ -753,11 +763,13 @@ int bnref_step_cells(const bnref_grid *gr, const bnref_params *pa, const uint8_t
     Y0 = (real *)malloc(sizeof(real) * m.nx);
     rc = detector(&m, Qn, Y0);
     if (rc) { free(Y0); return rc; }
+    for (n = 0; n < ncells; ++n)
+        if (cells[n] < 0 || (size_t)cells[n] >= plane) { free(Y0); return BNREF_EINVAL; }
+#pragma omp parallel for private(k) schedule(dynamic, 16) if (ncells >= 4096)
     for (n = 0; n < ncells; ++n) {
         int i, j;
         recon_t rc0, rw, re, rs, rn;
         real Qc[NV], res[4], DpW[NV], DmE[NV], DpS[NV], DmN[NV], dummy[NV];
-        if (cells[n] < 0 || (size_t)cells[n] >= plane) { free(Y0); return BNREF_EINVAL; }
         i = (int)(cells[n] % m.nx);
         j = (int)(cells[n] / m.nx);
         if (!is_fluid(&m, i, j)) {
@@ -805,6 +817,17 @@ int bnref_run(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid
     if (dt_out) *dt_out = dt;
     return rc;
 }
+
+/* Threads of the row sweeps (1 without OpenMP).  bnref_set_threads(n) with n >= 1 sets them;
+ * results do not depend on the count. */
+#ifdef _OPENMP
+#include <omp.h>
+int bnref_threads(void) { return omp_get_max_threads(); }
+void bnref_set_threads(int32_t n) { if (n >= 1) omp_set_num_threads(n); }
+#else
+int bnref_threads(void) { return 1; }
+void bnref_set_threads(int32_t n) { (void)n; }
+#endif
 
 /* ---- pieces exported for the oracle's own pins (unit tests) ---------------------------- */
 

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bnref.c")
 LIB = os.path.join(HERE, "libbnref.so")
 
-CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 OK, EINVAL, ENONPHYS, EUNSUPPORTED = 0, -1, -3, -4
 
@@ -75,6 +75,10 @@ def _bind(path):
     for name in ("bnref_detector", "bnref_cfl", "bnref_step", "bnref_step_cells", "bnref_run",
                  "bnref_flux", "bnref_matrix", "bnref_fluct", "bnref_reconstruct"):
         getattr(L, name).restype = ctypes.c_int
+    L.bnref_threads.argtypes = []
+    L.bnref_threads.restype = ctypes.c_int
+    L.bnref_set_threads.argtypes = [ctypes.c_int32]
+    L.bnref_set_threads.restype = None
     return L
 
 
@@ -85,6 +89,15 @@ def lib():
             build()
         _lib = _bind(LIB)
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's row sweeps use (OpenMP; results do not depend on it)."""
+    return int(lib().bnref_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().bnref_set_threads(int(n))
 
 
 # The literal forms of three passages that the oracle reads differently (compile-time switches of

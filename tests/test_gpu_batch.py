@@ -6,24 +6,17 @@ computes every cell with the same arithmetic whatever the partition), and within
 tolerance of the oracle.  Inputs: small members of the scenario families the tests and the
 ensemble workload use (dam breaks with obstacles, drops, water at rest over a step, ragged sizes).
 """
-import math
 
 import numpy as np
 import pytest
 
 from paper_1806_04960_amd import scenarios as sc
+from tests.parity import field_errors
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-11
 
 
-def field_errors(s, q_gpu, q_ref):
-    """Per-field max error over max(|oracle field|, acoustic scale), as in the single-grid parity
-    tests."""
-    c = math.sqrt(s.k0 / s.rho0)
-    scales = [s.rho0 * s.alpha_liq, s.rho0 * c * s.alpha_liq, s.rho0 * c * s.alpha_liq, 1.0]
-    return np.array([np.abs(q_gpu[k] - q_ref[k]).max() / max(np.abs(q_ref[k]).max(), scales[k])
-                     for k in range(4)])
 
 
 @pytest.fixture(scope="module")
