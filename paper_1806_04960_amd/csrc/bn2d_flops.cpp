@@ -6,7 +6,8 @@
 // way the kernel walks it, but without the kernel's redundant halo work: one reconstruction per
 // fluid cell, one solve per x- and y-edge with a fluid side, one update and one detector/CFL term
 // per fluid cell.  Loop-invariant constants (products of grid and model constants) are not
-// counted.  Build: g++ -O2 -std=c++17 -fPIC -shared.
+// counted.  Rows are walked in parallel (OpenMP), each thread counting its own; the counts are sums
+// of integers, so they do not depend on the thread count.  Build: g++ -O2 -std=c++17 -fopenmp -fPIC -shared.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -19,7 +20,7 @@ typedef bn::Counted real_t;
 #define BN2D_HOST_COUNT 1
 
 namespace bn {
-static unsigned long long g_ops = 0;
+static thread_local unsigned long long g_ops = 0;  // per thread: rows are counted in parallel
 struct Counted {
     double v;
     Counted() : v(0.0) {}
@@ -92,6 +93,7 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
     std::vector<Rec> rec(plane);
     unsigned long long c_rec = 0, c_x = 0, c_y = 0, c_upd = 0, c_red = 0, cells = 0;
 
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : c_rec)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             if (!fluid(i, j)) continue;
@@ -112,6 +114,7 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
         }
 
     std::vector<real_t> DpW(4 * plane), DmE(4 * plane), DpS(4 * plane), DmN(4 * plane);
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : c_x)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i <= nx; ++i) {
             const bool lf = fluid(i - 1, j), rf = fluid(i, j);
@@ -132,6 +135,7 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
                 if (rf) DpW[k * plane + (size_t)j * nx + i] = Dp[k];
             }
         }
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : c_y)
     for (int j = 0; j <= ny; ++j)
         for (int i = 0; i < nx; ++i) {
             const bool bf = fluid(i, j - 1), tf = fluid(i, j);
@@ -155,6 +159,7 @@ extern "C" int bn2d_count_flops(int nx, int ny, double x0, double x1, double y0,
             }
         }
     const real_t dtv(dt), dtdx(dt / K.dx), dtdy(dt / K.dy);
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : c_upd, c_red, cells)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             if (!fluid(i, j)) continue;

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libbn2d_flops.so")
 
 def build() -> str:
     tmp = LIB + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-w", "-o", tmp, SRC])
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-w", "-o", tmp, SRC])
     os.replace(tmp, LIB)
     return LIB
 
