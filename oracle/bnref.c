@@ -64,6 +64,11 @@
  *  [R19] Reflective wall: the ghost state is the interior edge state with its normal
  *        momentum negated (E-part and height copied); transmissive: a copy.  Solid cells
  *        are never updated.
+ *  [R21] A column's bottom y_L (the top of an obstacle, Sec. 3.5 and 5.7) may be given off the
+ *        grid, within half a cell of the top of its whole-cell solid run: the detector then
+ *        integrates alpha from y_L, the first fluid cell standing for the interval from y_L to
+ *        its top edge.  The cells themselves stay whole (solid iff the centre lies below the
+ *        obstacle's top).  Without given bottoms y_L is the top of the solid run.
  *
  * Literal forms (off by default; the test-suite builds them separately to show why [R12], [R14]
  * and [R18] depart from the printed text):
@@ -103,6 +108,7 @@ typedef struct {
     real g, k0, rho0, al, ag;
     int bc[4];
     const uint8_t *solid;
+    const double *ybot; /* bottom height y_L of each column [R21], or NULL */
 } model_t;
 
 /* ------------------------------------------------------------------------------------ */
@@ -385,20 +391,31 @@ static void estate(const model_t *m, int liquid, real Y0, real y, real e[NV])
     e[4] = y;
 }
 
-/* Free-surface detector [R6] (Sec. 3.5). */
+/* Free-surface detector [R6] (Sec. 3.5): y0 = y_L + the integral of the normalised volume fraction
+ * from the column's bottom y_L upwards.  [R21] y_L may lie inside the first fluid cell (a cut cell)
+ * or inside the solid cell below it: the first fluid cell's value then stands for the whole fluid
+ * interval from y_L to its top edge.  Written as the grid-aligned sum plus the correction of the
+ * bottom's offset d = y_L - (top of the solid run), weighted by the part of the first cell that is
+ * not liquid: d (1 - a_first).  A column whose first cell is full (a_first = 1) thus gets bitwise the
+ * grid-aligned value, so water at rest over a wall stays exactly at rest; an empty one gets y_L. */
 static int detector(const model_t *m, const double *Q, real *Y0)
 {
     size_t plane = (size_t)m->nx * m->ny;
     int i, j;
     for (i = 0; i < m->nx; ++i) {
         int jb = 0;
-        real sum = 0.0;
+        real sum = 0.0, first = 0.0, base;
         while (jb < m->ny && !is_fluid(m, i, jb)) ++jb;
         for (j = jb; j < m->ny; ++j) {
+            real a;
             if (!is_fluid(m, i, j)) return BNREF_EUNSUPPORTED; /* solid above fluid */
-            sum += (Q[3 * plane + (size_t)j * m->nx + i] - m->ag) / (m->al - m->ag);
+            a = (Q[3 * plane + (size_t)j * m->nx + i] - m->ag) / (m->al - m->ag);
+            if (j == jb) first = a;
+            sum += a;
         }
-        Y0[i] = (m->ylo + jb * m->dy) + m->dy * sum;
+        base = m->ylo + jb * m->dy;
+        Y0[i] = base + m->dy * sum;
+        if (m->ybot) Y0[i] += (m->ybot[i] - base) * (1.0 - first);
     }
     return BNREF_OK;
 }
@@ -610,9 +627,10 @@ static void update_cell(const model_t *m, const real Qn[NV], const recon_t *r, c
 /* Public entry points (test infrastructure)                                            */
 /* ------------------------------------------------------------------------------------ */
 
-static int make_model(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, model_t *m)
+static int make_model(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot,
+                      model_t *m)
 {
-    int k;
+    int i, k;
     if (!gr || !pa || gr->nx <= 0 || gr->ny <= 0 || !(gr->x1 > gr->x0) || !(gr->y1 > gr->y0)) return BNREF_EINVAL;
     if (!(pa->k0 > 0.0) || !(pa->rho0 > 0.0) || !(pa->alpha_gas > 0.0) || !(pa->alpha_liq > pa->alpha_gas)
         || !(pa->alpha_liq <= 1.0) || !(pa->cfl > 0.0) || !(pa->cfl <= 1.0) || !(pa->g >= 0.0))
@@ -627,14 +645,25 @@ static int make_model(const bnref_grid *gr, const bnref_params *pa, const uint8_
         m->bc[k] = pa->bc[k];
     }
     m->solid = solid;
+    m->ybot = ybot;
+    /* [R21] each bottom lies within half a cell of the top of its column's solid run */
+    if (ybot)
+        for (i = 0; i < m->nx; ++i) {
+            int jb = 0;
+            real d;
+            while (jb < m->ny && !is_fluid(m, i, jb)) ++jb;
+            d = ybot[i] - (m->ylo + jb * m->dy);
+            if (!(d >= -0.5 * m->dy && d < 0.5 * m->dy)) return BNREF_EINVAL;
+        }
     return BNREF_OK;
 }
 
-int bnref_detector(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *q, double *y0)
+int bnref_detector(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot,
+                   const double *q, double *y0)
 {
     model_t m;
     real *Y0;
-    int rc = make_model(gr, pa, solid, &m), i;
+    int rc = make_model(gr, pa, solid, ybot, &m), i;
     if (rc) return rc;
     Y0 = (real *)malloc(sizeof(real) * m.nx);
     rc = detector(&m, q, Y0);
@@ -651,7 +680,7 @@ int bnref_cfl(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid
     model_t m;
     size_t plane;
     real lam = 0.0, c;
-    int rc = make_model(gr, pa, solid, &m), i, j;
+    int rc = make_model(gr, pa, solid, NULL, &m), i, j;
     if (rc) return rc;
     plane = (size_t)m.nx * m.ny;
     c = sqrt(eos_c2(&m));
@@ -676,15 +705,15 @@ int bnref_cfl(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid
 
 /* One full explicit step Q^n -> Q^{n+1} with the given dt: detector, reconstruction of every
  * fluid cell, every edge fluctuation once, cell update.  Solid cells are copied. */
-int bnref_step(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *Qn,
-               double dt_in, double *Qout)
+int bnref_step(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot,
+               const double *Qn, double dt_in, double *Qout)
 {
     model_t m;
     real *Y0, dt = dt_in;
     recon_t *R;
     real *Dxm, *Dxp, *Dym, *Dyp;
     size_t plane;
-    int rc = make_model(gr, pa, solid, &m), i, j, k;
+    int rc = make_model(gr, pa, solid, ybot, &m), i, j, k;
     if (rc) return rc;
     if (!(dt_in > 0.0)) return BNREF_EINVAL;
     plane = (size_t)m.nx * m.ny;
@@ -749,14 +778,14 @@ done:
 /* The same update for a list of cells only (flat indices j*nx+i), each computed on its own
  * from Q^n: the checker for samples of grids too large for a full oracle step.
  * out is [4][ncells].  Solid cells return their input. */
-int bnref_step_cells(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *Qn,
-                     double dt_in, int64_t ncells, const int64_t *cells, double *out)
+int bnref_step_cells(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot,
+                     const double *Qn, double dt_in, int64_t ncells, const int64_t *cells, double *out)
 {
     model_t m;
     real *Y0, dt = dt_in;
     size_t plane;
     int64_t n;
-    int rc = make_model(gr, pa, solid, &m), k;
+    int rc = make_model(gr, pa, solid, ybot, &m), k;
     if (rc) return rc;
     if (!(dt_in > 0.0) || ncells < 0) return BNREF_EINVAL;
     plane = (size_t)m.nx * m.ny;
@@ -795,8 +824,8 @@ int bnref_step_cells(const bnref_grid *gr, const bnref_params *pa, const uint8_t
 
 /* n_steps steps with the CFL time step of the current state before each step [R10].
  * Q is updated in place; t_out receives the elapsed time and dt_out the last dt. */
-int bnref_run(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, double *Q, int32_t n_steps,
-              double *t_out, double *dt_out)
+int bnref_run(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot, double *Q,
+              int32_t n_steps, double *t_out, double *dt_out)
 {
     size_t plane;
     double *tmp, t = 0.0, dt = 0.0;
@@ -807,7 +836,7 @@ int bnref_run(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid
     for (s = 0; s < n_steps; ++s) {
         rc = bnref_cfl(gr, pa, solid, Q, NULL, &dt);
         if (rc) break;
-        rc = bnref_step(gr, pa, solid, Q, dt, tmp);
+        rc = bnref_step(gr, pa, solid, ybot, Q, dt, tmp);
         if (rc) break;
         memcpy(Q, tmp, sizeof(double) * 4 * plane);
         t += dt;
@@ -834,7 +863,7 @@ void bnref_set_threads(int32_t n) { (void)n; }
 static int pieces_model(const bnref_params *pa, model_t *m)
 {
     bnref_grid gr = {1, 1, 0.0, 1.0, 0.0, 1.0};
-    return make_model(&gr, pa, NULL, m);
+    return make_model(&gr, pa, NULL, NULL, m);
 }
 
 int bnref_flux(const bnref_params *pa, int32_t dir, const double *q, double *out)
@@ -892,14 +921,14 @@ int bnref_fluct(const bnref_params *pa, int32_t dir, const double *qm, const dou
 
 /* Reconstruction of cell (i, j): faces [4][5], E-parts [4][5], centre [5], limited
  * gradients gx[4], gy[4]; returns the second-order flag (0/1) or a negative error. */
-int bnref_reconstruct(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *Q,
-                      int32_t i, int32_t j, double dt, double *faces, double *eparts, double *centre,
-                      double *grad)
+int bnref_reconstruct(const bnref_grid *gr, const bnref_params *pa, const uint8_t *solid, const double *ybot,
+                      const double *Q, int32_t i, int32_t j, double dt, double *faces, double *eparts,
+                      double *centre, double *grad)
 {
     model_t m;
     real *Y0;
     recon_t r;
-    int rc = make_model(gr, pa, solid, &m), f, k;
+    int rc = make_model(gr, pa, solid, ybot, &m), f, k;
     if (rc) return rc;
     if (!is_fluid(&m, i, j)) return BNREF_EINVAL;
     Y0 = (real *)malloc(sizeof(real) * m.nx);

@@ -5,12 +5,14 @@ CPU-baseline leg of ``bench.py`` import this module.  The product path (the HIP 
 ``paper_1806_04960_amd``) never imports, links or calls it.
 
 Every function takes a *scenario*: any object with the attributes ``nx, ny, x0, x1, y0, y1``
-(grid), ``g, k0, rho0, alpha_liq, alpha_gas, cfl, bc`` (parameters) and ``solid``
-(``uint8 [ny, nx]`` or ``None``).  States are ``float64 [4, ny, nx]`` arrays holding
+(grid), ``g, k0, rho0, alpha_liq, alpha_gas, cfl, bc`` (parameters), ``solid``
+(``uint8 [ny, nx]`` or ``None``) and optionally ``bottom`` (``float64 [nx]``: each column's bottom
+height for the free-surface detector, or ``None``).  States are ``float64 [4, ny, nx]`` arrays holding
 (alpha rho, alpha rho u, alpha rho v, alpha).
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 import os
 import subprocess
@@ -61,16 +63,16 @@ def _bind(path):
     dp = P(ctypes.c_double)
     u8p = P(ctypes.c_uint8)
     gp, pp = P(_Grid), P(_Params)
-    L.bnref_detector.argtypes = [gp, pp, u8p, dp, dp]
+    L.bnref_detector.argtypes = [gp, pp, u8p, dp, dp, dp]
     L.bnref_cfl.argtypes = [gp, pp, u8p, dp, dp, dp]
-    L.bnref_step.argtypes = [gp, pp, u8p, dp, ctypes.c_double, dp]
-    L.bnref_step_cells.argtypes = [gp, pp, u8p, dp, ctypes.c_double, ctypes.c_int64,
+    L.bnref_step.argtypes = [gp, pp, u8p, dp, dp, ctypes.c_double, dp]
+    L.bnref_step_cells.argtypes = [gp, pp, u8p, dp, dp, ctypes.c_double, ctypes.c_int64,
                                    P(ctypes.c_int64), dp]
-    L.bnref_run.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, dp, dp]
+    L.bnref_run.argtypes = [gp, pp, u8p, dp, dp, ctypes.c_int32, dp, dp]
     L.bnref_flux.argtypes = [pp, ctypes.c_int32, dp, dp]
     L.bnref_matrix.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, dp, dp]
     L.bnref_fluct.argtypes = [pp, ctypes.c_int32, dp, dp, dp, dp, dp, dp]
-    L.bnref_reconstruct.argtypes = [gp, pp, u8p, dp, ctypes.c_int32, ctypes.c_int32,
+    L.bnref_reconstruct.argtypes = [gp, pp, u8p, dp, dp, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_double, dp, dp, dp, dp]
     for name in ("bnref_detector", "bnref_cfl", "bnref_step", "bnref_step_cells", "bnref_run",
                  "bnref_flux", "bnref_matrix", "bnref_fluct", "bnref_reconstruct"):
@@ -149,6 +151,16 @@ def _solid(s):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
+def _bottom(s):
+    b = getattr(s, "bottom", None)
+    if b is None:
+        return None, None
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if b.shape != (s.nx,):
+        raise ValueError(f"bottom shape {b.shape} != ({s.nx},)")
+    return b, _dp(b)
+
+
 def _state(s, q) -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=np.float64)
     if q.shape != (4, s.ny, s.nx):
@@ -164,8 +176,9 @@ def _check(rc: int, where: str):
 def detector(s, q) -> np.ndarray:
     q = _state(s, q)
     keep, sp = _solid(s)
+    keepb, bp = _bottom(s)
     y0 = np.zeros(s.nx)
-    _check(lib().bnref_detector(_grid(s), params_struct(s), sp, _dp(q), _dp(y0)), "detector")
+    _check(lib().bnref_detector(_grid(s), params_struct(s), sp, bp, _dp(q), _dp(y0)), "detector")
     return y0
 
 
@@ -182,8 +195,9 @@ def cfl(s, q, L=None):
 def step(s, q, dt: float, L=None) -> np.ndarray:
     q = _state(s, q)
     keep, sp = _solid(s)
+    keepb, bp = _bottom(s)
     out = np.empty_like(q)
-    _check((L or lib()).bnref_step(_grid(s), params_struct(s), sp, _dp(q), float(dt), _dp(out)), "step")
+    _check((L or lib()).bnref_step(_grid(s), params_struct(s), sp, bp, _dp(q), float(dt), _dp(out)), "step")
     return out
 
 
@@ -191,9 +205,10 @@ def step_cells(s, q, dt: float, cells) -> np.ndarray:
     """Q^{n+1} at the flat cell indices ``cells`` (j*nx + i); returns [4, len(cells)]."""
     q = _state(s, q)
     keep, sp = _solid(s)
+    keepb, bp = _bottom(s)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.empty((4, cells.size))
-    _check(lib().bnref_step_cells(_grid(s), params_struct(s), sp, _dp(q), float(dt), cells.size,
+    _check(lib().bnref_step_cells(_grid(s), params_struct(s), sp, bp, _dp(q), float(dt), cells.size,
                                   cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out)),
            "step_cells")
     return out
@@ -203,8 +218,9 @@ def run(s, q, n_steps: int, L=None):
     """Advance ``n_steps`` CFL steps; returns (state, elapsed time, last dt)."""
     q = _state(s, q).copy()
     keep, sp = _solid(s)
+    keepb, bp = _bottom(s)
     t, dt = ctypes.c_double(), ctypes.c_double()
-    _check((L or lib()).bnref_run(_grid(s), params_struct(s), sp, _dp(q), int(n_steps), ctypes.byref(t),
+    _check((L or lib()).bnref_run(_grid(s), params_struct(s), sp, bp, _dp(q), int(n_steps), ctypes.byref(t),
                            ctypes.byref(dt)), "run")
     return q, t.value, dt.value
 
@@ -231,6 +247,24 @@ def adjoint_fd(s, q, lam, dt: float, h=1e-6) -> np.ndarray:
                 qm[k, j, i] -= hk
                 diff = step(s, qp, dt) - step(s, qm, dt)
                 out[k, j, i] = float(np.sum(lam * diff)) / (2.0 * hk)
+    return out
+
+
+def adjoint_fd_bottom(s, q, lam, dt: float, columns, h=1e-6) -> np.ndarray:
+    """Gradient of <lam, step(q, dt)> with respect to the bottom heights of ``columns`` (the
+    scenario's ``bottom``, the detector's y_L), by central differences of the step (h in metres).
+    The bottoms must stay within half a cell of their solid runs' tops at +-h."""
+    q = _state(s, q)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    base = np.asarray(s.bottom, dtype=np.float64)
+    out = np.zeros(len(columns))
+    for n, i in enumerate(columns):
+        sp_, sm_ = copy.copy(s), copy.copy(s)
+        sp_.bottom = base.copy()
+        sm_.bottom = base.copy()
+        sp_.bottom[i] += h
+        sm_.bottom[i] -= h
+        out[n] = float(np.sum(lam * (step(sp_, q, dt) - step(sm_, q, dt)))) / (2.0 * h)
     return out
 
 
@@ -267,8 +301,9 @@ def reconstruct(s, q, i: int, j: int, dt: float):
     """Reconstruction of cell (i, j): dict of faces [4,5] (W,E,S,N), eparts, centre, gx, gy, so."""
     q = _state(s, q)
     keep, sp = _solid(s)
+    keepb, bp = _bottom(s)
     faces, ep, centre, grad = np.zeros((4, 5)), np.zeros((4, 5)), np.zeros(5), np.zeros(8)
-    rc = lib().bnref_reconstruct(_grid(s), params_struct(s), sp, _dp(q), int(i), int(j), float(dt),
+    rc = lib().bnref_reconstruct(_grid(s), params_struct(s), sp, bp, _dp(q), int(i), int(j), float(dt),
                                  _dp(faces), _dp(ep), _dp(centre), _dp(grad))
     _check(rc, "reconstruct")
     return {"faces": faces, "eparts": ep, "centre": centre, "gx": grad[:4], "gy": grad[4:], "so": bool(rc)}

@@ -45,6 +45,7 @@ class Scenario:
     cfl: float = CFL
     bc: tuple = (0, 0, 0, 0)          # W, E, S, N: 0 reflective, 1 transmissive
     solid: np.ndarray | None = None   # uint8 [ny, nx], 1 = solid
+    bottom: np.ndarray | None = None  # float64 [nx]: bottom height of each column (obstacle tops) or None
     q: np.ndarray | None = None       # float64 [4, ny, nx]
     steps: int = 0
     meta: dict = field(default_factory=dict)
@@ -72,7 +73,15 @@ class Scenario:
 
     def copy(self) -> "Scenario":
         return replace(self, solid=None if self.solid is None else self.solid.copy(),
+                       bottom=None if self.bottom is None else self.bottom.copy(),
                        q=None if self.q is None else self.q.copy(), meta=dict(self.meta))
+
+    def solid_tops(self) -> np.ndarray:
+        """Top of each column's bottom-attached solid run (the grid-aligned bottom)."""
+        if self.solid is None:
+            return np.full(self.nx, self.y0)
+        jb = np.where((self.solid == 0).any(axis=0), np.argmax(self.solid == 0, axis=0), self.ny)
+        return self.y0 + jb * self.dy
 
 
 def _rect(s: Scenario, xa, xb, ya, yb) -> np.ndarray:
@@ -245,14 +254,18 @@ def ensemble(seed: int = 0, count: int = 64, sizes=ENSEMBLE_SIZES):
     return out
 
 
-def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, theta=None):
+def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, theta=None,
+                wall_height: float = 0.4):
     """Reservoir released against a wall, the adjoint workload: [0,4] x [0,2], free-surface profile
     h(x) piecewise linear through theta_k = 0.6 + 0.1 U(-1, 1) at x_k = 3.5 k / (n_theta - 1);
     alpha is the liquid volume fraction of each cell below h(x_i) (two-level away from the surface,
     fractional in the cell the surface cuts); a one-cell solid wall of height 0.4 in the first
-    column right of x = 3.5; dry (gas) right of it.  Hydrostatic density below each column's
-    free surface (the detector's value), k0 = 6.54e5, at rest.  The profile values are kept in
-    meta["theta"]; ``theta`` given replaces the seeded ones (gradient checks)."""
+    column right of x = 3.5 (cells whose centre lies below its top are solid; the free-surface
+    detector takes the top itself as that column's bottom, so that the loss is differentiable in
+    it); dry (gas) right of it.  Hydrostatic density below each column's free surface (the
+    detector's value), k0 = 6.54e5, at rest.  The profile values are kept in meta["theta"];
+    ``theta`` given replaces the seeded ones (gradient checks); ``wall_height`` moves the wall's
+    top (within the cell that holds it)."""
     rng = np.random.default_rng(seed)
     theta = 0.6 + 0.1 * rng.uniform(-1.0, 1.0, n_theta) if theta is None else np.asarray(theta, float)
     n_theta = theta.size
@@ -264,6 +277,11 @@ def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, 
     solid[s.yc() < 0.4, iw] = 1
     s.solid = solid
     s.meta["wall_column"] = iw
+    s.meta["wall_height"] = float(wall_height)
+    s.bottom = s.solid_tops()
+    s.bottom[iw] = wall_height
+    if not abs(wall_height - s.solid_tops()[iw]) < 0.5 * s.dy:
+        raise ValueError("wall_height must lie within half a cell of the wall's rasterised top")
     hx = np.interp(xc, 3.5 * np.arange(n_theta) / (n_theta - 1), theta)
     hx[xc >= 3.5] = 0.0
     ybot = s.y0 + np.arange(ny) * s.dy
@@ -276,7 +294,10 @@ def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, 
     for i in range(nx):
         col_f = solid[:, i] == 0
         jb = int(np.argmax(col_f)) if col_f.any() else ny
-        y_surf = (s.y0 + jb * s.dy) + s.dy * float(frac[:, i].sum())
+        base = s.y0 + jb * s.dy
+        y_surf = base + s.dy * float(frac[:, i].sum())
+        if jb < ny:  # the detector's value with the column's bottom (the wall's top)
+            y_surf += (s.bottom[i] - base) * (1.0 - float(frac[jb, i]))
         liq = col_f & (yc < y_surf)
         rho[liq, i] = s.rho0 * np.exp(-a * (yc[liq] - y_surf))
     q = np.zeros((4, ny, nx))

@@ -26,13 +26,17 @@ def sanitized(tmp_path_factory):
 
 
 def write_case(path, s, q, steps, cells):
-    hdr = np.array([s.nx, s.ny, steps, len(cells), int(s.solid is not None), *s.bc], dtype="<i4")
+    bottom = getattr(s, "bottom", None)
+    hdr = np.array([s.nx, s.ny, steps, len(cells), int(s.solid is not None), *s.bc, int(bottom is not None)],
+                   dtype="<i4")
     d = np.array([s.x0, s.x1, s.y0, s.y1, s.g, s.k0, s.rho0, s.alpha_liq, s.alpha_gas, s.cfl], dtype="<f8")
     with open(path, "wb") as f:
         f.write(hdr.tobytes())
         f.write(d.tobytes())
         if s.solid is not None:
             f.write(np.ascontiguousarray(s.solid, dtype=np.uint8).tobytes())
+        if bottom is not None:
+            f.write(np.ascontiguousarray(bottom, dtype="<f8").tobytes())
         f.write(np.ascontiguousarray(q, dtype="<f8").tobytes())
         f.write(np.asarray(cells, dtype="<i8").tobytes())
 
@@ -47,11 +51,13 @@ def cases():
     drop = sc.circular_drop(12, 12)
     # (the 32 x 16 and 20 x 10 dam breaks are coarse enough that the gas cell above the collapsing
     # column empties at t = 0.035 s; the runs stop well before)
+    # an obstacle whose top lies off the grid (the detector's cut first cells)
+    wall = sc.wall_impact(0, 32, 16)
     return [(db, 15), (noisy, 10), (tx, 8), (drop, 5), (sc.dam_break_small(1, 1), 3),
-            (sc.dam_break_small(1, 7), 3), (sc.dam_break_small(7, 1), 3)]
+            (sc.dam_break_small(1, 7), 3), (sc.dam_break_small(7, 1), 3), (wall, 10)]
 
 
-@pytest.mark.parametrize("idx", range(7))
+@pytest.mark.parametrize("idx", range(8))
 def test_sanitized_oracle_runs_clean_and_matches_the_plain_build(oracle, sanitized, idx):
     exe, d = sanitized
     s, steps = cases()[idx]
