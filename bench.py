@@ -299,10 +299,13 @@ class WallLoad:
         for _ in range(self.N):
             self.sim.step(self.dt)
 
-    def gradient(self, q_init=None, N=None, store_all=False):
+    def gradient(self, q_init=None, N=None, store_all=False, bottom=False):
+        """dJ/dq0 (and, with ``bottom``, dJ/dy_L of the columns' bottoms: the wall's height is its
+        column's entry)."""
         from paper_1806_04960_amd import bn2d
         return bn2d.trajectory_gradient(self.sim, self.q0 if q_init is None else q_init, self.dt,
-                                        self.N if N is None else N, self.w, self.seg, store_all=store_all)
+                                        self.N if N is None else N, self.w, self.seg, store_all=store_all,
+                                        bottom=bottom)
 
     def measure(self, reps=5):
         """Whole-gradient cost (forward with checkpoints + recomputation + reverse) over a plain
@@ -324,10 +327,15 @@ class WallLoad:
                 out.append(a.elapsed_time(b))
             return median(out)
 
+        # the workload's gradient: the 64 profile values come from dJ/dq0 through the state's
+        # construction (host), the wall's height from the summed bottom adjoints of its column
         fwd_ms = med(self.forward_plain, reps)
-        grad_ms = med(self.gradient, reps)
-        grad_all_ms = med(lambda: self.gradient(store_all=True), reps)
-        assert torch.equal(self.gradient(store_all=True), self.gradient())
+        grad_ms = med(lambda: self.gradient(bottom=True), reps)
+        grad_all_ms = med(lambda: self.gradient(store_all=True, bottom=True), reps)
+        g_all, gb_all = self.gradient(store_all=True, bottom=True)
+        g_ck, gb_ck = self.gradient(bottom=True)
+        assert torch.equal(g_all, g_ck) and torch.equal(gb_all, gb_ck)
+        dj_dhw = float(gb_ck[self.s.meta["wall_column"]])
         lam = torch.randn((4, self.s.ny, self.s.nx), dtype=torch.float64, device="cuda")
         out = torch.empty_like(lam)
 
@@ -349,7 +357,8 @@ class WallLoad:
                             f"fixed dt, checkpoints every {self.seg}",
                 "forward_ms": fwd_ms, "gradient_ms": grad_ms, "cost_ratio": grad_ms / fwd_ms,
                 "gradient_all_states_ms": grad_all_ms, "cost_ratio_all_states": grad_all_ms / fwd_ms,
-                "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3, "timing": f"median of {reps} repeats"}
+                "step_us": step_ms * 1e3, "adjoint_step_us": adj_ms * 1e3, "timing": f"median of {reps} repeats",
+                "dJ_dwall_height": dj_dhw}
 
     def close(self):
         self.sim.close()

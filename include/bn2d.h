@@ -101,6 +101,17 @@ int bn_get_y0(bn_ctx *ctx, double *y0_host);
 /* Synchronise and report BN_ENONPHYS if any step met a non-physical state. */
 int bn_status(bn_ctx *ctx);
 
+/* Bottom height y_L of each column for the free-surface detector (Sec. 3.5: y0 = y_L + the integral
+ * of the normalised volume fraction from y_L up), e.g. the top of an obstacle that does not lie on a
+ * grid line (the wall of Sec. 5.7).  y_bottom_host: nx doubles (host), each within half a cell of the
+ * top of its column's solid run: -dy/2 <= y_L - (y0 + jb dy) < dy/2 with jb the column's solid cells
+ * (else BN_EINVAL, nothing changed); NULL restores the default, the top of each solid run.  The
+ * cells stay whole; the detector takes the column's first fluid cell to cover the interval from y_L
+ * to its top edge:  y0 = (y0 + jb dy) + dy sum_j a_j + (y_L - y0 - jb dy)(1 - a_jb),
+ * a = (alpha - alpha_gas)/(alpha_liq - alpha_gas), so a full first cell gives the grid-aligned value
+ * exactly.  Applies from the next step on; synchronises the stream. */
+int bn_set_bottom(bn_ctx *ctx, const double *y_bottom_host);
+
 /* Launch shape of the step kernel.  Wavefronts march strips of 60 columns and claim rows in blocks
  * of rows_per_block (1..4096, 0 = default 4); the launch is persistent with `wavefronts`
  * wavefronts (1..65536, 0 = default: as many as the device holds at once, or fewer for a small grid,
@@ -124,11 +135,15 @@ const char *bn_strerror(int code);
  * the context's state.  dt is held fixed (the CFL maximum is not differentiated); the free-surface
  * height is differentiated as the real column sum of Sec. 3.5; at the scheme's non-smooth points
  * (limiter min/max, |u|, sign, the second-order and liquid switches, walls) the branch the step
- * takes is differentiated.  The library allocates its scratch (about 75 doubles per cell) on the
- * first call and keeps it until bn_destroy.  Asynchronous on the context's stream.  Errors:
- * BN_EINVAL (null pointer, dt <= 0 or not finite), BN_ENOMEM, BN_EHIP.  A non-physical q_dev gives
- * non-finite values. */
-int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev);
+ * takes is differentiated.  grad_bottom_dev: NULL, or a caller-owned device buffer of nx doubles
+ * that receives the model-parameter gradient (d Q^{n+1} / d y_L)^T lam_next_dev of the columns'
+ * bottom heights y_L (bn_set_bottom; e.g. an obstacle's height): y_L enters the step only through
+ * its column's free surface, dy0/dy_L = 1 - a of the column's first fluid cell (0 for a fully solid
+ * column).  The library allocates its scratch (about 77 doubles per cell) on the first call and keeps
+ * it until bn_destroy.  Asynchronous on the context's stream.  Errors: BN_EINVAL (null pointer, dt <= 0
+ * or not finite), BN_ENOMEM, BN_EHIP.  A non-physical q_dev gives non-finite values. */
+int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
+                    double *grad_bottom_dev);
 
 /* bn_adjoint_step without any allocation, for callers that cannot allocate device memory (code
  * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments, result
@@ -141,7 +156,8 @@ int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev
  * uses that GPU's one array: calls that overlap in time on one GPU (other streams, other contexts,
  * other threads) race and give wrong results; calls ordered on one stream, or synchronised, do not.
  * Calls no hipMalloc, hipFree or allocating library routine. */
-int bn_adjoint_step_noalloc(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev);
+int bn_adjoint_step_noalloc(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
+                            double *grad_bottom_dev);
 
 /* ---- Batches: many grids advanced by one launch per step -------------------------------------
  * A batch holds `count` independent grids (members) of any sizes, parameters and masks, e.g. an
@@ -173,6 +189,9 @@ int bn_batch_get_y0(bn_batch *batch, int32_t member, double *y0_host);
 /* Synchronise; BN_ENONPHYS with *member set to the first member that met a non-physical state
  * (member may be NULL; -1 when all are fine). */
 int bn_batch_status(bn_batch *batch, int32_t *member);
+
+/* Bottom heights of member `member`, as bn_set_bottom. */
+int bn_batch_set_bottom(bn_batch *batch, int32_t member, const double *y_bottom_host);
 
 /* Launch shape, as bn_set_launch / bn_get_launch. */
 int bn_batch_set_launch(bn_batch *batch, int32_t rows_per_block, int32_t wavefronts);

@@ -16,10 +16,11 @@ LIB_PATH = os.environ.get("BN2D_LIB", os.path.join(HERE, "libbn2d.so"))
 BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
-           "bn_get_time", "bn_get_y0", "bn_status", "bn_set_launch", "bn_get_launch", "bn_destroy",
-           "bn_strerror", "bn_adjoint_step", "bn_adjoint_step_noalloc", "bn_batch_create", "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run",
-           "bn_batch_get_time", "bn_batch_get_y0", "bn_batch_status", "bn_batch_set_launch",
-           "bn_batch_get_launch", "bn_batch_destroy")
+           "bn_get_time", "bn_get_y0", "bn_status", "bn_set_bottom", "bn_set_launch", "bn_get_launch",
+           "bn_destroy", "bn_strerror", "bn_adjoint_step", "bn_adjoint_step_noalloc", "bn_batch_create",
+           "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run", "bn_batch_get_time", "bn_batch_get_y0",
+           "bn_batch_status", "bn_batch_set_bottom", "bn_batch_set_launch", "bn_batch_get_launch",
+           "bn_batch_destroy")
 
 
 class BnError(RuntimeError):
@@ -64,8 +65,9 @@ def lib():
         L.bn_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.bn_destroy.argtypes = [vp]
         L.bn_destroy.restype = None
-        L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp]
-        L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp]
+        L.bn_set_bottom.argtypes = [vp, dp]
+        L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+        L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
         i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
@@ -77,6 +79,7 @@ def lib():
         L.bn_batch_get_time.argtypes = [vp, i32, dp, dp]
         L.bn_batch_get_y0.argtypes = [vp, i32, dp]
         L.bn_batch_status.argtypes = [vp, pi32]
+        L.bn_batch_set_bottom.argtypes = [vp, i32, dp]
         L.bn_batch_set_launch.argtypes = [vp, i32, i32]
         L.bn_batch_get_launch.argtypes = [vp, pi32, pi32]
         L.bn_batch_destroy.argtypes = [vp]
@@ -106,7 +109,8 @@ class Simulation:
     """One context of the library on the current CUDA (HIP) device and stream.
 
     ``scenario`` provides the grid (nx, ny, x0, x1, y0, y1), the parameters (g, k0, rho0,
-    alpha_liq, alpha_gas, cfl, bc) and the solid mask (uint8 [ny, nx] or None)."""
+    alpha_liq, alpha_gas, cfl, bc), the solid mask (uint8 [ny, nx] or None) and optionally the
+    columns' bottom heights (``bottom``, float64 [nx] or None; ``bn_set_bottom``)."""
 
     def __init__(self, scenario, stream=None, rows_per_block: int | None = None, wavefronts: int | None = None):
         import numpy as np
@@ -125,8 +129,21 @@ class Simulation:
         check(lib().bn_create(ctypes.byref(grid_of(scenario)), ctypes.byref(params_of(scenario)), solid,
                               ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)), "bn_create")
         self._ctx = ctx
+        if getattr(scenario, "bottom", None) is not None:
+            self.set_bottom(scenario.bottom)
         if rows_per_block is not None or wavefronts is not None:
             self.set_launch(rows_per_block or 0, wavefronts or 0)
+
+    def set_bottom(self, bottom):
+        """Bottom height of each column for the free-surface detector (nx values; None resets)."""
+        import numpy as np
+        if bottom is None:
+            check(lib().bn_set_bottom(self._ctx, None), "bn_set_bottom")
+            return
+        b = np.ascontiguousarray(bottom, dtype=np.float64)
+        if b.shape != (self.nx,):
+            raise ValueError(f"bottom must hold {self.nx} values")
+        check(lib().bn_set_bottom(self._ctx, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "bn_set_bottom")
 
     # -- state -------------------------------------------------------------------------------
     def set_state(self, q):
@@ -155,17 +172,20 @@ class Simulation:
     def run(self, n_steps: int):
         check(lib().bn_run(self._ctx, int(n_steps)), "bn_run")
 
-    def adjoint_step(self, q, lam_next, dt: float, out=None):
+    def adjoint_step(self, q, lam_next, dt: float, out=None, grad_bottom=None):
         """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} for the step of length dt from state q
-        (``bn_adjoint_step``).  q, lam_next: contiguous float64 CUDA tensors [4, ny, nx]."""
-        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out)
+        (``bn_adjoint_step``).  q, lam_next: contiguous float64 CUDA tensors [4, ny, nx].  With
+        ``grad_bottom`` (a float64 CUDA tensor [nx]) also (dQ^{n+1}/dy_L)^T lambda^{n+1} of the
+        columns' bottom heights."""
+        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out, grad_bottom)
 
-    def adjoint_step_noalloc(self, q, lam_next, dt: float, out):
+    def adjoint_step_noalloc(self, q, lam_next, dt: float, out, grad_bottom=None):
         """The same adjoint through ``bn_adjoint_step_noalloc``: the library's fixed scratch array,
         no allocation (the caller passes ``out``)."""
-        return self._adjoint(lib().bn_adjoint_step_noalloc, "bn_adjoint_step_noalloc", q, lam_next, dt, out)
+        return self._adjoint(lib().bn_adjoint_step_noalloc, "bn_adjoint_step_noalloc", q, lam_next, dt, out,
+                             grad_bottom)
 
-    def _adjoint(self, fn, name, q, lam_next, dt, out):
+    def _adjoint(self, fn, name, q, lam_next, dt, out, grad_bottom):
         import torch
         shape = (4, self.ny, self.nx)
         if out is None:
@@ -173,8 +193,14 @@ class Simulation:
         for arg, t in (("q", q), ("lam_next", lam_next), ("out", out)):
             if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
                 raise ValueError(f"{arg} must be a contiguous float64 CUDA tensor of shape {shape}")
+        gb = None
+        if grad_bottom is not None:
+            if not (grad_bottom.is_cuda and grad_bottom.dtype == torch.float64 and grad_bottom.is_contiguous()
+                    and tuple(grad_bottom.shape) == (self.nx,)):
+                raise ValueError(f"grad_bottom must be a contiguous float64 CUDA tensor of shape ({self.nx},)")
+            gb = ctypes.c_void_p(grad_bottom.data_ptr())
         check(fn(self._ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(lam_next.data_ptr()), float(dt),
-                 ctypes.c_void_p(out.data_ptr())), name)
+                 ctypes.c_void_p(out.data_ptr()), gb), name)
         return out
 
     def time(self):
@@ -246,6 +272,11 @@ class Batch:
         check(lib().bn_batch_create(n, grids, params, solids, ctypes.c_void_p(self._stream.cuda_stream),
                                     ctypes.byref(b)), "bn_batch_create")
         self._b = b
+        for k, s in enumerate(scenarios):
+            if getattr(s, "bottom", None) is not None:
+                bot = np.ascontiguousarray(s.bottom, dtype=np.float64)
+                check(lib().bn_batch_set_bottom(self._b, k, bot.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                      "bn_batch_set_bottom")
         if rows_per_block is not None or wavefronts is not None:
             check(lib().bn_batch_set_launch(self._b, int(rows_per_block or 0), int(wavefronts or 0)),
                   "bn_batch_set_launch")
@@ -356,11 +387,13 @@ def _trajectory_forward(sim, q0, dt: float, N: int, w, seg: int, with_loss: bool
     return J, ck
 
 
-def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int):
-    """dJ/dq0 from the checkpoints: each segment, last first, recomputed and reversed."""
+def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
+    """dJ/dq0 from the checkpoints: each segment, last first, recomputed and reversed (and, into
+    ``gbot`` if given, the sum over the steps of the bottom heights' adjoints)."""
     import torch
 
     lam = torch.zeros_like(ck[0])
+    g1 = None if gbot is None else torch.empty_like(gbot)
     buf = [None] * seg
     for c in range(len(ck) - 1, -1, -1):
         n0 = c * seg
@@ -372,7 +405,9 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int):
             buf[k] = sim.get_state()
         for k in range(m - 1, -1, -1):
             lam = lam + w  # dJ/dQ^{n0+k+1}
-            lam = sim.adjoint_step(buf[k], lam, dt)
+            lam = sim.adjoint_step(buf[k], lam, dt, grad_bottom=g1)
+            if gbot is not None:
+                gbot += g1
     sim.set_state(ck[0])
     return lam
 
@@ -391,20 +426,29 @@ def _check_trajectory(N, seg, q0, weights):
 
 
 def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int = 20, with_loss: bool = False,
-                        store_all: bool = False):
+                        store_all: bool = False, bottom: bool = False):
     """Gradient of J = sum_{n=1..N} <weights, Q^n> over N steps of fixed length dt from q0 with
     respect to q0, by the discrete adjoint (``bn_adjoint_step``): the forward run keeps the state
     every ``segment`` steps, then each segment, last first, is recomputed from its checkpoint and
     reversed step by step.  Memory: N/segment + segment states.  With ``store_all`` the forward run
     keeps every state instead (N states, no recomputation: one forward step fewer per step where
     device memory allows it).  Returns dJ/dq0, or (J, dJ/dq0) with ``with_loss`` (J then also costs a
-    reduction per forward step).  Leaves the context at q0 (its elapsed time restarted)."""
+    reduction per forward step); with ``bottom`` also dJ/dy_L of the columns' bottom heights
+    (bn_set_bottom), appended to the result.  Leaves the context at q0 (its elapsed time
+    restarted)."""
+    import torch
+
     N, seg = _check_trajectory(n_steps, segment, q0, weights)
     w = weights.contiguous()
     dt = float(dt)
-    if store_all:
-        import torch
+    gbot = torch.zeros(sim.nx, dtype=torch.float64, device=q0.device) if bottom else None
 
+    def result(J, lam):
+        out = (float(J), lam) if with_loss else (lam,)
+        out = out + ((gbot,) if bottom else ())
+        return out if len(out) > 1 else out[0]
+
+    if store_all:
         states = [q0.detach().clone()]
         sim.set_state(states[0])
         J = torch.zeros((), dtype=torch.float64, device=q0.device)
@@ -417,13 +461,16 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
                 if k + 1 < N:
                     states.append(q)
         lam = torch.zeros_like(states[0])
+        g1 = torch.empty_like(gbot) if bottom else None
         for n in range(N - 1, -1, -1):
-            lam = sim.adjoint_step(states[n], lam + w, dt)
+            lam = sim.adjoint_step(states[n], lam + w, dt, grad_bottom=g1)
+            if bottom:
+                gbot += g1
         sim.set_state(states[0])
-        return (float(J), lam) if with_loss else lam
+        return result(J, lam)
     J, ck = _trajectory_forward(sim, q0, dt, N, w, seg, with_loss)
-    lam = _trajectory_reverse(sim, ck, dt, N, w, seg)
-    return (float(J), lam) if with_loss else lam
+    lam = _trajectory_reverse(sim, ck, dt, N, w, seg, gbot)
+    return result(J, lam)
 
 
 def trajectory_loss_function():

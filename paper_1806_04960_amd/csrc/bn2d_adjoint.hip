@@ -8,7 +8,8 @@
 //   D-+(e)      = edge_x / edge_y of the two edge states of e (a wall or solid side mirrors the
 //                 fluid side's state)
 //   Q^{n+1}_c   = Q^n_c - dt/dx (D+_W + D-_E + fdiff) - dt/dy (D+_S + D-_N + gdiff) - dt vol
-// is reversed in five passes, one thread per cell or edge, through library-owned planes:
+// is reversed in five passes (a sixth for the bottom heights' adjoint), one thread per cell, edge or
+// column, through library-owned planes:
 //   1. adj_rec_kernel     recompute Rec_c (the edge states the edges need), 21 planes
 //   2. adj_edge_kernel    per x- and y-edge (one launch for both kinds): recompute D-+, reverse
 //                         it with the adjoints of the two cells' updates, and write the adjoints
@@ -22,8 +23,12 @@
 //   5. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
 //                         fluid cells whose stencil holds c (of a first-order neighbour only
 //                         c's own entry) + the detector's dy/(alpha_l -
-//                         alpha_g) times its column's y0 adjoint (alpha only); solid cells pass
-//                         lambda through (their state is copied and never read)
+//                         alpha_g) times its column's y0 adjoint (alpha only; (dy - d)/(alpha_l -
+//                         alpha_g) in the first fluid cell of a column whose bottom lies d off the
+//                         grid); solid cells pass lambda through (their state is copied and never
+//                         read)
+//   6. adj_bottom_kernel  (if asked) the adjoint of each column's bottom height: its y0 adjoint
+//                         times dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,6 +43,7 @@ struct AdjArgs {
     double *lam;            // lambda^n, 4 planes
     const uint8_t *solid;   // nx*ny or null
     const int *jb;          // first fluid row per column
+    const double *dbot;     // per column: bottom height minus the top of its solid run, or null
     const long long *S;     // fixed-point free-surface integral of Q^n per column
     double fix_inv;
     double dt, dtdx, dtdy;
@@ -47,6 +53,7 @@ struct AdjArgs {
     double *y0b;            // 1 plane (0 for solid cells)
     double *sob;            // 1 plane: 1 where the fluid cell's reconstruction is second order
     double *colb;           // [ceil(ny / kColRows)][nx] partial column sums
+    double *gbot;           // [nx] adjoint of the bottom heights, or null
 };
 
 constexpr int kColRows = 32;
@@ -69,9 +76,18 @@ __device__ __forceinline__ int flags_at(const AdjArgs &a, int i, int j)
     return cell_flags(i, j, a.K.nx, a.K.ny, a.K.bc, fluid_at(a, i, j));
 }
 
+// 1 - (alpha - alpha_g)/(alpha_l - alpha_g) of column i's first fluid cell (0 for a full cell)
+__device__ __forceinline__ double first_gap(const AdjArgs &a, int i)
+{
+    const size_t n = (size_t)a.K.nx * a.K.ny;
+    return (a.K.al - a.q[3 * n + (size_t)a.jb[i] * a.K.nx + i]) * a.K.inv_dal;
+}
+
 __device__ __forceinline__ double y0_of(const AdjArgs &a, int i)
 {
-    return (a.K.ylo + a.jb[i] * a.K.dy) + a.K.dy * ((double)a.S[i] * a.fix_inv);
+    double v = (a.K.ylo + a.jb[i] * a.K.dy) + a.K.dy * ((double)a.S[i] * a.fix_inv);
+    if (a.dbot && a.jb[i] < a.K.ny) v += a.dbot[i] * first_gap(a, i);
+    return v;
 }
 
 // The 3 x 3 stencil of cell (i, j): states (outside the grid: the benign (1, 0, 0, 1), never used)
@@ -340,15 +356,26 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
             }
         double col = 0.0;
         for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
-        out[3] += a.K.dy / (a.K.al - a.K.ag) * col;
+        const double dy_eff = (a.dbot && j == a.jb[i]) ? a.K.dy - a.dbot[i] : a.K.dy;
+        out[3] += dy_eff / (a.K.al - a.K.ag) * col;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k];
 }
 
+// adjoint of each column's bottom height (thread = column)
+__global__ __launch_bounds__(64) void adj_bottom_kernel(AdjArgs a)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= a.K.nx) return;
+    double col = 0.0;
+    for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
+    a.gbot[i] = a.jb[i] < a.K.ny ? col * first_gap(a, i) : 0.0;
+}
+
 }  // namespace bn
 
-// Launch the five passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
+// Launch the passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
 namespace bn {
 constexpr int kAdjPlanes = kRecPlanes + kFacePlanes + 36 + 2;
 }
@@ -359,8 +386,8 @@ size_t bn_adjoint_scratch(int nx, int ny)
 }
 
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
-                             const uint8_t *solid, const int *jb, const long long *S, double fix_inv, double dt,
-                             double *scratch, hipStream_t stream)
+                             const uint8_t *solid, const int *jb, const double *dbot, const long long *S,
+                             double fix_inv, double dt, double *scratch, double *gbot, hipStream_t stream)
 {
     bn::AdjArgs a;
     a.K = K;
@@ -369,6 +396,8 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.lam = lam;
     a.solid = solid;
     a.jb = jb;
+    a.dbot = dbot;
+    a.gbot = gbot;
     a.S = S;
     a.fix_inv = fix_inv;
     a.dt = dt;
@@ -390,5 +419,6 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
                        0, stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
+    if (gbot) hipLaunchKernelGGL(bn::adj_bottom_kernel, dim3((K.nx + 63) / 64), dim3(64), 0, stream, a);
     return hipGetLastError();
 }

@@ -23,14 +23,15 @@ __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int
                                      long long nrows, double *Ts_in, double *Ts_acc, const bn::StripInfo *strips,
                                      int nstrips);
 __global__ void zero_kernel(long long *p, int n);
-__global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, double *y0, Consts K);
+__global__ void y0_kernel(const long long *S, const int *jb, const double *dbot, const double *Q, double fix_inv,
+                          double *y0, Consts K);
 }  // namespace bn
 
 // the discrete adjoint's passes (bn2d_adjoint.hip)
 size_t bn_adjoint_scratch(int nx, int ny);
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
-                             const uint8_t *solid, const int *jb, const long long *S, double fix_inv, double dt,
-                             double *scratch, hipStream_t stream);
+                             const uint8_t *solid, const int *jb, const double *dbot, const long long *S,
+                             double fix_inv, double dt, double *scratch, double *gbot, hipStream_t stream);
 
 namespace {
 
@@ -83,6 +84,8 @@ struct Grid {
     double *q[2] = {nullptr, nullptr};
     uint8_t *solid = nullptr;
     int *jb = nullptr;
+    std::vector<int> jb_host;           // first fluid row of each column
+    double *dbot = nullptr;             // [nx] bottom offsets, allocated by bn_*set_bottom
     long long *S = nullptr;             // [3][nx]
     unsigned long long *lam = nullptr;  // [3]
     double *t = nullptr;
@@ -192,7 +195,7 @@ namespace {
 void free_batch(bn_batch *b)
 {
     for (Grid &g : b->g) {
-        void *ptrs[] = {g.q[0], g.q[1], g.solid, g.jb, g.S, g.lam, g.t, g.flag, g.y0, g.dt, g.adj, g.adjS};
+        void *ptrs[] = {g.q[0], g.q[1], g.solid, g.jb, g.dbot, g.S, g.lam, g.t, g.flag, g.y0, g.dt, g.adj, g.adjS};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -371,6 +374,7 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
         Grid &g = b->g[k];
         g.grid = grids[k];
         g.params = params[k];
+        g.jb_host = jbs[k];
         const int nx = g.grid.nx, ny = g.grid.ny;
         const size_t plane = (size_t)nx * ny;
         ALLOC(g.q[0], sizeof(double) * 4 * plane);
@@ -512,11 +516,43 @@ int bn_batch_get_y0(bn_batch *b, int32_t member, double *y0_host)
     Grid &g = b->g[member];
     const int nx = g.grid.nx;
     hipLaunchKernelGGL(bn::y0_kernel, dim3((nx + 255) / 256), dim3(256), 0, b->stream, g.S + (size_t)b->m3 * nx,
-                       g.jb, g.dev.fix_inv, g.y0, g.dev.K);
+                       g.jb, g.dbot, g.q[b->cur], g.dev.fix_inv, g.y0, g.dev.K);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(y0_host, g.y0, sizeof(double) * nx, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return BN_OK;
+}
+
+int bn_batch_set_bottom(bn_batch *b, int32_t member, const double *y_bottom_host)
+{
+    if (bad_member(b, member)) return BN_EINVAL;
+    Grid &g = b->g[member];
+    const int nx = g.grid.nx;
+    const double dy = (g.grid.y1 - g.grid.y0) / g.grid.ny;
+    std::vector<double> d(nx, 0.0);
+    if (y_bottom_host) {
+        for (int i = 0; i < nx; ++i) {
+            d[i] = y_bottom_host[i] - (g.grid.y0 + g.jb_host[i] * dy);
+            if (!(d[i] >= -0.5 * dy && d[i] < 0.5 * dy)) return BN_EINVAL;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (!y_bottom_host) {
+        if (g.dbot) HIP_TRY(hipFree(g.dbot));
+        g.dbot = nullptr;
+    } else {
+        if (!g.dbot) {
+            const hipError_t e = hipMalloc(&g.dbot, sizeof(double) * nx);
+            if (e != hipSuccess) {
+                g.dbot = nullptr;
+                g_last_hip_error = std::string("hipMalloc(bottom): ") + hipGetErrorString(e);
+                return BN_ENOMEM;
+            }
+        }
+        HIP_TRY(hipMemcpy(g.dbot, d.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+    }
+    g.dev.dbot = g.dbot;
+    return write_tables(b);
 }
 
 int bn_batch_status(bn_batch *b, int32_t *member)
@@ -628,6 +664,12 @@ int bn_status(bn_ctx *c)
     return bn_batch_status(c->b, nullptr);
 }
 
+int bn_set_bottom(bn_ctx *c, const double *y_bottom_host)
+{
+    if (!c) return BN_EINVAL;
+    return bn_batch_set_bottom(c->b, 0, y_bottom_host);
+}
+
 int bn_set_launch(bn_ctx *c, int32_t rows_per_block, int32_t wavefronts)
 {
     if (!c) return BN_EINVAL;
@@ -640,7 +682,8 @@ int bn_get_launch(bn_ctx *c, int32_t *rows_per_block, int32_t *wavefronts)
     return bn_batch_get_launch(c->b, rows_per_block, wavefronts);
 }
 
-int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev)
+int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
+                    double *grad_bottom_dev)
 {
     if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
     bn_batch *b = c->b;
@@ -665,8 +708,8 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
                        g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, S, g.dev.fix_inv, dt, g.adj,
-                              b->stream));
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
+                              g.adj, grad_bottom_dev, b->stream));
     return BN_OK;
 }
 
@@ -704,7 +747,8 @@ int scratch_address(double **out)
 
 extern "C" {
 
-int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev)
+int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
+                            double *grad_bottom_dev)
 {
     if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
     bn_batch *b = c->b;
@@ -724,8 +768,8 @@ int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_ne
     hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
                        g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, S, g.dev.fix_inv, dt, base,
-                              b->stream));
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
+                              base, grad_bottom_dev, b->stream));
     return BN_OK;
 }
 

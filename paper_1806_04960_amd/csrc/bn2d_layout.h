@@ -13,6 +13,7 @@ struct Member {
     double *q[2];                   // state buffers; q[cur] holds the current state
     const uint8_t *solid;           // nx*ny mask or null
     const int *jb;                  // first fluid row of each column
+    const double *dbot;             // per column: bottom height minus the top of its solid run, or null
     long long *S[3];                // fixed-point free-surface integrals (read m3, accumulate m3+1, clear m3+2)
     unsigned long long *lam[3];     // CFL rate maxima (same rotation), bits of a non-negative double
     double *t;                      // elapsed time

@@ -270,7 +270,11 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     double y0c = 0.0;
     if (colin) {
         const Member &M = member_ref(mab);
-        y0c = (M.K.ylo + M.jb[i] * M.K.dy) + M.K.dy * ((double)M.S[a.m3][i] * M.fix_inv);
+        const int jbi = M.jb[i];
+        y0c = (M.K.ylo + jbi * M.K.dy) + M.K.dy * ((double)M.S[a.m3][i] * M.fix_inv);
+        // a bottom off the grid (Sec. 3.5): the first fluid cell stands for the interval from the
+        // bottom to its top edge; its offset counts where that cell is not liquid
+        if (M.dbot && jbi < ny) y0c += M.dbot[i] * ((M.K.al - Qp[3 * plane + (size_t)jbi * nx + i]) * M.K.inv_dal);
     }
     unsigned long long *desc = slot >= 0 ? control_at(ca).desc + slot : nullptr;
     bool outstanding = false, last = slot < 0;
@@ -727,11 +731,16 @@ __global__ void zero_kernel(long long *p, int n)
     if (s < n) p[s] = 0;
 }
 
-// y0 = y_bottom + dy * integral per column, for bn_get_y0.
-__global__ void y0_kernel(const long long *S, const int *jb, double fix_inv, double *y0, Consts K)
+// y0 = y_bottom + dy * integral per column (with the offset of a bottom off the grid, as the step
+// forms it from state Q), for bn_get_y0.
+__global__ void y0_kernel(const long long *S, const int *jb, const double *dbot, const double *Q, double fix_inv,
+                          double *y0, Consts K)
 {
     const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < K.nx) y0[i] = (K.ylo + jb[i] * K.dy) + K.dy * ((double)S[i] * fix_inv);
+    if (i >= K.nx) return;
+    double v = (K.ylo + jb[i] * K.dy) + K.dy * ((double)S[i] * fix_inv);
+    if (dbot && jb[i] < K.ny) v += dbot[i] * ((K.al - Q[(size_t)3 * K.nx * K.ny + (size_t)jb[i] * K.nx + i]) * K.inv_dal);
+    y0[i] = v;
 }
 
 }  // namespace bn

@@ -309,6 +309,23 @@ def wall_impact(seed: int = 0, nx: int = 512, ny: int = 256, n_theta: int = 64, 
     return s
 
 
+def tank_with_wall(top: float, surface: float = 0.5, nx: int = 40, ny: int = 32, column: int = 13,
+                   offset: float = 0.0) -> Scenario:
+    """Water at rest below ``surface`` in a closed 2 m x 1 m tank (g = 9.81, k0 = 2.78e5, alpha = 1 in
+    the liquid), with a one-column wall in ``column`` whose cells below ``top`` (by their centres) are
+    solid; the column's bottom height for the free-surface detector is the top of that solid run plus
+    ``offset`` cells (a wall top off the grid)."""
+    s = Scenario("tank_wall", nx, ny, 0.0, 2.0, 0.0, 1.0, k0=2.78e5, alpha_liq=1.0)
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[s.yc() < top, column] = 1
+    s.solid = solid
+    X, Y = np.meshgrid(s.xc(), s.yc())
+    s = _fill(s, Y <= surface)
+    s.bottom = s.solid_tops()
+    s.bottom[column] += offset * s.dy
+    return s
+
+
 def wall_impact_theta_vjp(s: Scenario, lam0) -> np.ndarray:
     """dJ/dtheta from dJ/dq0 (``lam0``, [4, ny, nx]) for a ``wall_impact`` state: the chain rule
     through its construction, with the same switches held fixed as it takes them (which cells the

@@ -286,3 +286,103 @@ def test_profile_gradient_matches_differences(bn, torch_cuda, kind):
             print(f"theta ({kind}): adjoint {ad:.10e} fd {fd2:.10e} rel {abs(ad - fd2) / abs(fd2):.2e} "
                   f"fd h vs h/2 {spread:.2e}", flush=True)
             assert abs(ad - fd2) <= (TOL + 2 * spread) * abs(fd2)
+
+
+# ---- the gradient with respect to the columns' bottom heights (an obstacle's top) ----------------
+
+def wall_with_liquid(nx, ny, a_first=0.35):
+    """The wall-impact state with liquid over the wall: the wall column's first fluid cell partly
+    liquid (a_first of the way from gas to liquid), the two cells above it liquid, then generic."""
+    s = sc.wall_impact(0, nx, ny)
+    iw = s.meta["wall_column"]
+    jb = int(np.argmax(s.solid[:, iw] == 0))
+    q = s.q
+    q[3, jb:jb + 3, iw] = s.alpha_liq
+    q[3, jb, iw] = s.alpha_gas + a_first * (s.alpha_liq - s.alpha_gas)
+    q[0, jb:jb + 3, iw] = q[3, jb:jb + 3, iw] * s.rho0
+    return sc.generic_state(s, seed=5), iw
+
+
+def entry_fd(oracle, s, lam, dt, k, j, i, h):
+    qp, qm = s.q.copy(), s.q.copy()
+    qp[k, j, i] += h
+    qm[k, j, i] -= h
+    return float(np.sum(lam * (oracle.step(s, qp, dt) - oracle.step(s, qm, dt)))) / (2 * h)
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 8), (24, 12)])
+def test_bottom_gradient_matches_the_oracle(oracle, bn, torch_cuda, nx, ny):
+    torch = torch_cuda
+    s, iw = wall_with_liquid(nx, ny)
+    dt = 0.9 * oracle.cfl(s, s.q)[1]
+    lam = np.random.default_rng(9).normal(size=s.q.shape)
+    cols = list(range(s.nx))
+    ref = oracle.adjoint_fd_bottom(s, s.q, lam, dt, cols, h=1e-7)
+    with bn.Simulation(s) as sim:
+        gb = torch.full((s.nx,), float("nan"), dtype=torch.float64, device="cuda")
+        lam_n = sim.adjoint_step(torch.from_numpy(s.q).cuda(), torch.from_numpy(lam).cuda(), dt, grad_bottom=gb)
+        got, lam_n = gb.cpu().numpy(), lam_n.cpu().numpy()
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    print(f"{nx}x{ny}: bottom gradient {got[iw]:.6e} vs differences {ref[iw]:.6e}, max error {err:.2e} "
+          f"of {scale:.3e}", flush=True)
+    assert abs(ref[iw]) > 1e-3 and err <= TOL
+    # the state adjoint of the wall column's cells (whose first fluid cell's alpha reaches the free
+    # surface with the weight the bottom's offset sets): entries whose difference quotients at h and
+    # h/10 agree to 1e-7 (away from the scheme's kinks, which partly filled cells sit near)
+    jb = int(np.argmax(s.solid[:, iw] == 0))
+    checked = 0
+    for j in range(jb, min(jb + 4, s.ny)):
+        for k in range(4):
+            hk = 1.0 if k == 3 else abs(s.q[0, j, iw])
+            d1, d2 = (entry_fd(oracle, s, lam, dt, k, j, iw, h * hk) for h in (1e-6, 1e-7))
+            if abs(d1 - d2) > 1e-7 * max(abs(d2), 1.0):
+                continue
+            checked += 1
+            assert abs(lam_n[k, j, iw] - d2) <= TOL * max(abs(d2), np.abs(lam_n[k]).max()), (k, j)
+    assert checked >= 8
+
+
+def test_wall_height_gradient_of_the_wall_load_over_40_steps(bn, torch_cuda):
+    """dJ/dh_w of the wall-impact workload's loss (time-integrated pressure in front of the wall,
+    512 x 256, fixed dt) over 40 steps: the summed bottom-height adjoints of the wall column against
+    central differences of J in the wall's height, from the initial state and from a smooth one."""
+    torch = torch_cuda
+    from paper_1806_04960_amd import bn2d
+    for kind in ("initial", "smooth"):
+        s = sc.wall_impact(0)
+        if kind == "smooth":
+            s = sc.smooth_state(s)
+        iw = s.meta["wall_column"]
+        with bn.Simulation(s) as sim:
+            q0 = torch.from_numpy(s.q).cuda()
+            sim.set_state(q0)
+            dt = sim.compute_dt()
+            w = torch.zeros((4, s.ny, s.nx), dtype=torch.float64, device="cuda")
+            w[0, :, iw - 1] = dt * s.dy * s.k0 / s.rho0
+            w[3, :, iw - 1] = -dt * s.dy * s.k0
+            w *= torch.from_numpy(s.fluid()).cuda()
+            N = 40
+            lam, gbot = bn2d.trajectory_gradient(sim, q0, dt, N, w, 20, bottom=True)
+            g = float(gbot[iw])
+
+            def J(h_w):
+                b = s.bottom.copy()
+                b[iw] = h_w
+                sim.set_bottom(b)
+                sim.set_state(q0)
+                acc = torch.zeros((), dtype=torch.float64, device="cuda")
+                for _ in range(N):
+                    sim.step(dt)
+                    acc += (w * sim.get_state()).sum()
+                return float(acc)
+
+            hw = s.bottom[iw]
+            h = 1e-6
+            fd1 = (J(hw + h) - J(hw - h)) / (2 * h)
+            fd2 = (J(hw + h / 2) - J(hw - h / 2)) / h
+        spread = abs(fd1 - fd2) / abs(fd2)
+        err = abs(g - fd2) / abs(fd2)
+        print(f"{kind}: dJ/dh_w adjoint {g:.8e}, differences {fd2:.8e} (h vs h/2 {spread:.1e}), error {err:.1e}",
+              flush=True)
+        assert abs(fd2) > 0 and err <= 1e-6 + 2 * spread

@@ -312,3 +312,41 @@ def test_mirror_symmetry_across_strips(bn, torch_cuda):
     ey = np.abs(q - my).reshape(4, -1).max(axis=1) / scale
     print(f"drop mirror errors x {ex} y {ey}", flush=True)
     assert ex.max() < 1e-12 and ey.max() < 1e-12
+
+
+# ---- obstacle tops off the grid (the detector's bottom heights, bn_set_bottom) -----------------
+
+@pytest.mark.parametrize("offset", [-0.4, 0.3])
+def test_rest_over_an_off_grid_wall(oracle, bn, torch_cuda, offset):
+    """Water at rest over a wall whose top lies off the grid: kept at rest to round-off for 1000 steps
+    (velocities below 1e-11 m/s, as beside any obstacle), bitwise the run with the grid-aligned top
+    (the wall column's first fluid cell is full), and a wall standing above the water: its column's
+    free surface is the wall's top."""
+    s = sc.tank_with_wall(0.3, surface=0.5, offset=offset)
+    plain = s.copy()
+    plain.bottom = None
+    qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 1000)
+    qp, _, _, y0p = gpu_run(bn, torch_cuda, plain, 1000)
+    assert np.array_equal(qg, qp) and np.array_equal(y0g, y0p)
+    fl = s.fluid()
+    assert np.abs(qg[1] / qg[0])[fl].max() < 1e-11 and np.abs(qg[2] / qg[0])[fl].max() < 1e-11
+    assert np.abs(qg[0] - s.q[0])[fl].max() / s.rho0 < 1e-12
+    dry = sc.tank_with_wall(0.7, surface=0.4, offset=offset)
+    qd, _, _, y0d = gpu_run(bn, torch_cuda, dry, 200)
+    assert y0d[13] == pytest.approx(dry.bottom[13], abs=1e-15)
+    assert np.abs(qd[1] / qd[0])[dry.fluid()].max() < 1e-11
+
+
+def test_wall_impact_with_its_wall_top_against_the_oracle(oracle, bn, torch_cuda):
+    """The wall-impact workload (wall top 0.4 m, 0.2 cells above the grid line at 512 x 256; here
+    on coarser grids where it lies 0.4 cells above and 0.2 below the grid line) over 150 steps: the
+    liquid crosses
+    the wall column, whose first fluid cell fills and drains."""
+    for nx, ny in ((64, 32), (128, 64)):
+        s = sc.wall_impact(0, nx, ny)
+        qg, tg, dtg, y0g = gpu_run(bn, torch_cuda, s, 150)
+        qo, to, dto = oracle.run(s, s.q, 150)
+        assert_parity(s, qg, qo)
+        iw = s.meta["wall_column"]
+        assert qo[3, :, iw].max() > 0.5  # the wall column holds liquid
+        np.testing.assert_allclose(y0g, oracle.detector(s, qo), rtol=0, atol=1e-12)

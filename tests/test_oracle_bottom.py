@@ -19,18 +19,8 @@ from scipy import integrate
 from paper_1806_04960_amd import scenarios as sc
 
 
-def tank_with_wall(top, surface=0.5, nx=40, ny=32, column=13, alpha_liq=1.0):
-    """Water at rest below `surface` in a closed 2 m x 1 m tank (g = 9.81), with a one-column wall
-    in `column` whose top is `top` (cells below their centre solid; the detector's bottom = top)."""
-    s = sc.Scenario("tank_wall", nx, ny, 0.0, 2.0, 0.0, 1.0, k0=2.78e5, alpha_liq=alpha_liq)
-    solid = np.zeros((ny, nx), np.uint8)
-    solid[s.yc() < top, column] = 1
-    s.solid = solid
-    X, Y = np.meshgrid(s.xc(), s.yc())
-    s = sc._fill(s, Y <= surface)
-    s.bottom = s.solid_tops()
-    s.bottom[column] = top
-    return s
+def tank_with_wall(top, surface=0.5, nx=40, ny=32, column=13):
+    return sc.tank_with_wall(top, surface, nx, ny, column)
 
 
 def test_bottom_at_the_solid_tops_is_the_grid_aligned_detector(oracle):

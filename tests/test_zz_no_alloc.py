@@ -43,13 +43,16 @@ def test_noalloc_adjoint_equals_the_allocating_one_on_two_calls(bn, torch_cuda):
         with bn.Simulation(s) as sim:
             sim.set_state(q)
             dt = 0.9 * sim.compute_dt()
-            ref = sim.adjoint_step(q, lam, dt)
+            gref = torch.zeros(s.nx, dtype=torch.float64, device="cuda")
+            ref = sim.adjoint_step(q, lam, dt, grad_bottom=gref)
             out = torch.full_like(q, float("nan"))
-            sim.adjoint_step_noalloc(q, lam, dt, out)
+            gout = torch.full_like(gref, float("nan"))
+            sim.adjoint_step_noalloc(q, lam, dt, out, grad_bottom=gout)
             torch.cuda.synchronize()
         ref, out = ref.cpu().numpy(), out.cpu().numpy()
         assert np.all(np.isfinite(out))
         assert np.array_equal(out, ref), np.abs(out - ref).max()
+        assert torch.equal(gout, gref)
 
 
 def test_noalloc_adjoint_rejects_a_grid_beyond_its_array(bn, torch_cuda):
