@@ -413,12 +413,23 @@ def adjoint_main(args):
         st = sc.wall_impact(0, theta=theta)
         return torch.from_numpy((sc.smooth_state(st) if kind == "smooth" else st).q).cuda()
 
-    def record(entry, ad, fd1, fd2, out):
-        spread = abs(fd1 - fd2) / abs(fd2) if fd2 else None
-        # a quotient that moves by more than 1e-4 between h and h/2 straddles a kink: reported,
-        # not a check of the gradient
-        entry.update({"adjoint": ad, "fd": fd2, "rel": abs(ad - fd2) / abs(fd2) if fd2 else None,
-                      "fd_h_vs_h2": spread, "kink": spread is None or spread > 1e-4})
+    def record(entry, ad, fds, out):
+        """fds: central-difference quotients at decreasing steps h (a sweep over three decades).
+        Where the trajectory crosses one of the scheme's kinks within +-h (limiter min/max, the
+        liquid/gas and second-order switches) the quotients move with h; they then approach the
+        adjoint as h shrinks rather than agreeing with each other.  A defect of the adjoint shows as
+        the opposite: quotients that agree with each other ten times better than with the adjoint."""
+        hs = sorted(fds, reverse=True)
+        vals = [fds[h] for h in hs]
+        ref = vals[-1]
+        rel = [abs(ad - v) / abs(v) if v else None for v in vals]
+        spread = [abs(a - b) / abs(b) if b else None for a, b in zip(vals, vals[1:])]
+        kink = any(x is None or x > 1e-4 for x in spread)
+        err = min((r for r in rel if r is not None), default=None)
+        sp = min((x for x in spread if x is not None), default=None)
+        defect = err is not None and sp is not None and err > 1e-4 and sp < err / 10
+        entry.update({"adjoint": ad, "fd": ref, "rel": rel[-1], "h": hs, "fd_sweep": vals, "rel_sweep": rel,
+                      "spread_sweep": spread, "kink": kink, "defect": defect})
         out.append(entry)
         print(f"# check {len(out) - 1}: {entry}", file=sys.stderr, flush=True)
 
@@ -430,17 +441,31 @@ def adjoint_main(args):
         d[:, j0:j0 + 24, i0:i0 + 24] = rng.normal(size=(4, 24, 24))
         d *= scale
         dd = torch.from_numpy(d).cuda()
-        qa, h = q_of[kind], 1e-7
-        fd1 = (W.loss(qa + h * dd) - W.loss(qa - h * dd)) / (2 * h)
-        fd2 = (W.loss(qa + h / 2 * dd) - W.loss(qa - h / 2 * dd)) / h
-        record({"wrt": "q0", "state": kind, "patch": [j0, i0]}, float(np.sum(g_of[kind] * d)), fd1, fd2, checks)
+        qa = q_of[kind]
+        fds = {h: (W.loss(qa + h * dd) - W.loss(qa - h * dd)) / (2 * h) for h in (1e-6, 1e-7, 1e-8)}
+        record({"wrt": "q0", "state": kind, "patch": [j0, i0]}, float(np.sum(g_of[kind] * d)), fds, checks)
     for m in range(2 * args.fd_directions):
         kind = "smooth" if m % 2 else "initial"
         dth = rng.normal(size=theta0.size)
-        h = 1e-6
-        fd1 = (W.loss(q_theta(theta0 + h * dth, kind)) - W.loss(q_theta(theta0 - h * dth, kind))) / (2 * h)
-        fd2 = (W.loss(q_theta(theta0 + h / 2 * dth, kind)) - W.loss(q_theta(theta0 - h / 2 * dth, kind))) / h
-        record({"wrt": "theta", "state": kind}, float(gth_of[kind] @ dth), fd1, fd2, checks)
+        fds = {h: (W.loss(q_theta(theta0 + h * dth, kind)) - W.loss(q_theta(theta0 - h * dth, kind))) / (2 * h)
+               for h in (1e-5, 1e-6, 1e-7)}
+        record({"wrt": "theta", "state": kind}, float(gth_of[kind] @ dth), fds, checks)
+    # the wall's height (its column's bottom), from both states
+    iwall = s.meta["wall_column"]
+    hw0 = float(s.bottom[iwall])
+
+    def loss_hw(hw, kind, N=None):
+        b = s.bottom.copy()
+        b[iwall] = hw
+        W.sim.set_bottom(b)
+        J = W.loss(q_of[kind], N)
+        W.sim.set_bottom(s.bottom)
+        return J
+
+    for kind in ("initial", "smooth"):
+        _, gb = W.gradient(q_of[kind], bottom=True)
+        fds = {h: (loss_hw(hw0 + h, kind) - loss_hw(hw0 - h, kind)) / (2 * h) for h in (1e-5, 1e-6, 1e-7)}
+        record({"wrt": "wall_height", "state": kind}, float(gb[iwall]), fds, checks)
     # the same theta directions over a horizon on which J is smooth in theta (40 steps)
     N_short = 40
     short = []
@@ -450,12 +475,16 @@ def adjoint_main(args):
         gq = W.gradient(q_of[kind], N=N_short).cpu().numpy()
         gth = sc.wall_impact_theta_vjp(s, sc.smooth_state_vjp(s, gq) if kind == "smooth" else gq)
         dth = rng.normal(size=theta0.size)
-        h = 1e-7
-        fd1 = (W.loss(q_theta(theta0 + h * dth, kind), N_short) - W.loss(q_theta(theta0 - h * dth, kind), N_short)) / (2 * h)
-        fd2 = (W.loss(q_theta(theta0 + h / 2 * dth, kind), N_short)
-               - W.loss(q_theta(theta0 - h / 2 * dth, kind), N_short)) / h
-        record({"wrt": "theta", "state": kind, "steps": N_short}, float(gth @ dth), fd1, fd2, short)
+        fds = {h: (W.loss(q_theta(theta0 + h * dth, kind), N_short) - W.loss(q_theta(theta0 - h * dth, kind), N_short))
+               / (2 * h) for h in (1e-6, 1e-7, 5e-8)}
+        record({"wrt": "theta", "state": kind, "steps": N_short}, float(gth @ dth), fds, short)
+    for kind in ("initial", "smooth"):
+        _, gb = W.gradient(q_of[kind], N=N_short, bottom=True)
+        fds = {h: (loss_hw(hw0 + h, kind, N_short) - loss_hw(hw0 - h, kind, N_short)) / (2 * h)
+               for h in (1e-6, 1e-7, 5e-8)}
+        record({"wrt": "wall_height", "state": kind, "steps": N_short}, float(gb[iwall]), fds, short)
     W.close()
+    defects = [c for c in checks + short if c["defect"]]
     adj_ms = cost["adjoint_step_us"] / 1e3
     line = {
         "metric": "FP64 cell updates/sec",
@@ -472,9 +501,13 @@ def adjoint_main(args):
         "data": "synthetic",
         "config": {"workload": cost["workload"], "nx": s.nx, "ny": s.ny},
         "adjoint": dict(cost, grad_theta_norm=float(np.linalg.norm(gth_of["initial"])), fd_checks=checks,
-                        fd_checks_theta_40_steps=short),
+                        fd_checks_40_steps=short, defects=len(defects)),
     }
     print(json.dumps(line), flush=True)
+    if defects:
+        print(f"# {len(defects)} gradient checks look like adjoint defects (difference quotients agree with "
+              f"each other ten times better than with the adjoint)", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 def main():

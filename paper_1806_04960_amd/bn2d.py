@@ -393,7 +393,8 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
     import torch
 
     lam = torch.zeros_like(ck[0])
-    g1 = None if gbot is None else torch.empty_like(gbot)
+    # one row of bottom adjoints per step, summed once at the end
+    gsteps = None if gbot is None else torch.empty((N, gbot.numel()), dtype=gbot.dtype, device=gbot.device)
     buf = [None] * seg
     for c in range(len(ck) - 1, -1, -1):
         n0 = c * seg
@@ -405,9 +406,9 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
             buf[k] = sim.get_state()
         for k in range(m - 1, -1, -1):
             lam = lam + w  # dJ/dQ^{n0+k+1}
-            lam = sim.adjoint_step(buf[k], lam, dt, grad_bottom=g1)
-            if gbot is not None:
-                gbot += g1
+            lam = sim.adjoint_step(buf[k], lam, dt, grad_bottom=None if gsteps is None else gsteps[n0 + k])
+    if gbot is not None and N > 0:
+        gbot += gsteps.sum(dim=0)
     sim.set_state(ck[0])
     return lam
 
@@ -461,11 +462,11 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
                 if k + 1 < N:
                     states.append(q)
         lam = torch.zeros_like(states[0])
-        g1 = torch.empty_like(gbot) if bottom else None
+        gsteps = torch.empty((N, sim.nx), dtype=torch.float64, device=q0.device) if bottom else None
         for n in range(N - 1, -1, -1):
-            lam = sim.adjoint_step(states[n], lam + w, dt, grad_bottom=g1)
-            if bottom:
-                gbot += g1
+            lam = sim.adjoint_step(states[n], lam + w, dt, grad_bottom=None if gsteps is None else gsteps[n])
+        if bottom and N > 0:
+            gbot += gsteps.sum(dim=0)
         sim.set_state(states[0])
         return result(J, lam)
     J, ck = _trajectory_forward(sim, q0, dt, N, w, seg, with_loss)

@@ -8,8 +8,7 @@
 //   D-+(e)      = edge_x / edge_y of the two edge states of e (a wall or solid side mirrors the
 //                 fluid side's state)
 //   Q^{n+1}_c   = Q^n_c - dt/dx (D+_W + D-_E + fdiff) - dt/dy (D+_S + D-_N + gdiff) - dt vol
-// is reversed in five passes (a sixth for the bottom heights' adjoint), one thread per cell, edge or
-// column, through library-owned planes:
+// is reversed in five passes, one thread per cell, edge or column, through library-owned planes:
 //   1. adj_rec_kernel     recompute Rec_c (the edge states the edges need), 21 planes
 //   2. adj_edge_kernel    per x- and y-edge (one launch for both kinds): recompute D-+, reverse
 //                         it with the adjoints of the two cells' updates, and write the adjoints
@@ -27,8 +26,9 @@
 //                         alpha_g) in the first fluid cell of a column whose bottom lies d off the
 //                         grid); solid cells pass lambda through (their state is copied and never
 //                         read)
-//   6. adj_bottom_kernel  (if asked) the adjoint of each column's bottom height: its y0 adjoint
-//                         times dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g)
+//                         and (if asked) the adjoint of each column's bottom height: its y0
+//                         adjoint times dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g),
+//                         written by the column's first fluid cell
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -358,19 +358,14 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
         for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
         const double dy_eff = (a.dbot && j == a.jb[i]) ? a.K.dy - a.dbot[i] : a.K.dy;
         out[3] += dy_eff / (a.K.al - a.K.ag) * col;
+        // the column's bottom height reaches the step through its free surface only:
+        // dy0/dy_L = 1 - a of the first fluid cell (written by that cell's thread)
+        if (a.gbot && j == a.jb[i]) a.gbot[i] = col * first_gap(a, i);
+    } else if (a.gbot && j == a.K.ny - 1 && a.jb[i] == a.K.ny) {
+        a.gbot[i] = 0.0;  // a column without fluid cells
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k];
-}
-
-// adjoint of each column's bottom height (thread = column)
-__global__ __launch_bounds__(64) void adj_bottom_kernel(AdjArgs a)
-{
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= a.K.nx) return;
-    double col = 0.0;
-    for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
-    a.gbot[i] = a.jb[i] < a.K.ny ? col * first_gap(a, i) : 0.0;
 }
 
 }  // namespace bn
@@ -419,6 +414,5 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
                        0, stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
-    if (gbot) hipLaunchKernelGGL(bn::adj_bottom_kernel, dim3((K.nx + 63) / 64), dim3(64), 0, stream, a);
     return hipGetLastError();
 }
