@@ -19,6 +19,7 @@ __global__ void step_kernel(StepArgs a);
 __global__ void reduce_kernel(const double *Q, const uint8_t *solid, long long *S, double fix_scale,
                               unsigned long long *lam_slot, int *flag, Consts K, int H);
 __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K);
+__global__ void colsum_kernel(const double *Q, const uint8_t *solid, long long *S, double fix_scale, Consts K, int H);
 __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
                                      long long nrows, double *Ts_in, double *Ts_acc, const bn::StripInfo *strips,
                                      int nstrips);
@@ -335,6 +336,19 @@ int query_dt(bn_batch *b, Grid &g)
 }
 
 bool bad_member(const bn_batch *b, int32_t k) { return !b || k < 0 || k >= (int32_t)b->g.size(); }
+
+// The fixed-point free-surface integral of a given state into S (nx words, cleared first).
+constexpr int kColsumRows = 16;
+int adjoint_colsum(bn_batch *b, Grid &g, const double *q_dev, long long *S)
+{
+    const int nx = g.grid.nx, ny = g.grid.ny;
+    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 255) / 256), dim3(256), 0, b->stream, S, nx);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(bn::colsum_kernel, dim3((nx + 63) / 64, (ny + kColsumRows - 1) / kColsumRows), dim3(64), 0,
+                       b->stream, q_dev, g.solid, S, g.dev.fix_scale, g.dev.K, kColsumRows);
+    HIP_TRY(hipGetLastError());
+    return BN_OK;
+}
 
 }  // namespace
 
@@ -702,12 +716,8 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     }
     // the free-surface integral of the given state, exactly as a step from it would use it
     long long *S = g.adjS;
-    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 2 + 255) / 256), dim3(256), 0, b->stream, S, nx + 2);
-    HIP_TRY(hipGetLastError());
-    const int H = kReduceRows;
-    hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
-                       g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
-    HIP_TRY(hipGetLastError());
+    const int rc = adjoint_colsum(b, g, q_dev, S);
+    if (rc) return rc;
     HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
                               g.adj, grad_bottom_dev, b->stream));
     return BN_OK;
@@ -761,13 +771,9 @@ int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_ne
     const int rc = scratch_address(&base);
     if (rc) return rc;
     long long *S = reinterpret_cast<long long *>(base + planes);
-    // the array keeps the previous call's contents: the integrals must start at zero
-    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 2 + 255) / 256), dim3(256), 0, b->stream, S, nx + 2);
-    HIP_TRY(hipGetLastError());
-    const int H = kReduceRows;
-    hipLaunchKernelGGL(bn::reduce_kernel, dim3((nx + 63) / 64, (ny + H - 1) / H), dim3(64), 0, b->stream, q_dev,
-                       g.solid, S, g.dev.fix_scale, (unsigned long long *)(S + nx), (int *)(S + nx + 1), g.dev.K, H);
-    HIP_TRY(hipGetLastError());
+    // (the array keeps the previous call's contents: the integrals are cleared first)
+    const int rc2 = adjoint_colsum(b, g, q_dev, S);
+    if (rc2) return rc2;
     HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
                               base, grad_bottom_dev, b->stream));
     return BN_OK;

@@ -103,7 +103,8 @@ BN_DEV void abs_a1(const Consts &K, real_t u, real_t v, const real_t d[4], real_
 }
 
 // sign(A2(u, v)) r  =  sum_m r_m sign(lambda_m) (l_m . r),  lambda = (v-c, v, v, v+c), sign(0) = 0.
-BN_DEV void sign_a2(const Consts &K, real_t u, real_t v, const real_t r[4], real_t out[4])
+// `sub`: |v| < c is known (then sign(v - c) = -1 and sign(v + c) = 1 exactly).
+BN_DEV void sign_a2(const Consts &K, real_t u, real_t v, const real_t r[4], real_t out[4], bool sub)
 {
     const real_t c = K.c;
     const real_t l1 = ((c + v) * K.inv2c) * r[0] - r[2] * K.inv2c - K.half_rho0 * r[3];
@@ -111,7 +112,12 @@ BN_DEV void sign_a2(const Consts &K, real_t u, real_t v, const real_t r[4], real
     const real_t l3 = r[3] * K.inv_c2;
     const real_t l5 = ((c - v) * K.inv2c) * r[0] + r[2] * K.inv2c - K.half_rho0 * r[3];
     const real_t sv = sgn(v);
-    const real_t w1 = sgn(v - c) * l1, w2 = sv * l2, w3 = sv * l3, w5 = sgn(v + c) * l5;
+    real_t slo = -1.0, shi = 1.0;
+    if (!sub) {
+        slo = sgn(v - c);
+        shi = sgn(v + c);
+    }
+    const real_t w1 = slo * l1, w2 = sv * l2, w3 = sv * l3, w5 = shi * l5;
     out[0] = w1 + K.k0 * w3 + w5;
     out[1] = u * w1 + w2 + u * w5;
     out[2] = (v - c) * w1 + v * K.k0 * w3 + (v + c) * w5;
@@ -179,8 +185,13 @@ BN_DEV real_t b3(const Consts &K, const real_t qa[4], real_t e1a, real_t aEa, re
 // wavefront on the device (a uniform branch).
 #ifdef BN2D_HOST_COUNT
 BN_DEV bool y_jump(real_t ym, real_t yp) { return ym != yp; }
+BN_DEV bool any_lane(bool p) { return p; }
+BN_DEV bool all_lanes(bool p) { return p; }
 #else
 BN_DEV bool y_jump(double ym, double yp) { return __ballot(ym != yp) != 0ull; }
+// whether p holds in some (every) active lane of the wavefront: a uniform branch condition
+BN_DEV bool any_lane(bool p) { return __ballot(p) != 0ull; }
+BN_DEV bool all_lanes(bool p) { return __ballot(!p) == 0ull; }
 #endif
 
 // y-edge: well-balanced Osher-Romberg (Sec. 3.3, Romberg l = 3 of Sec. 3.1):
@@ -227,9 +238,11 @@ BN_DEV void edge_y(const Consts &K, const real_t qm[4], real_t e1m, real_t aEm, 
     R2[3] += v34 * (qp[3] - q12[3]);
     R3[3] += 0.5 * (v14 + v34) * d[3];
     real_t S1[4], S2[4], S3[4];
-    sign_a2(K, u14, v14, R1, S1);
-    sign_a2(K, u34, v34, R2, S2);
-    sign_a2(K, u12, v12, R3, S3);
+    // subsonic in every lane at the three nodes (the usual case): the outer eigenvalues' signs are known
+    const bool sub = all_lanes(fabs(v14) < K.c && fabs(v34) < K.c && fabs(v12) < K.c);
+    sign_a2(K, u14, v14, R1, S1, sub);
+    sign_a2(K, u34, v34, R2, S2, sub);
+    sign_a2(K, u12, v12, R3, S3, sub);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const real_t V = (4.0 / 3.0) * S1[k] + (4.0 / 3.0) * S2[k] - (1.0 / 3.0) * S3[k];
@@ -271,7 +284,9 @@ BN_DEV void reconstruct(const Consts &K, const S &st, int j, real_t y0c, real_t 
     const real_t yc = K.ylo + (j + 0.5) * K.dy;
     const bool liquid = yc < y0c;
     const real_t aE = liquid ? K.al : K.ag;
-    const real_t rE0 = liquid ? K.rho0 * exp(-K.a * (yc - y0c)) : K.rho0;
+    // (the exponential only where some lane holds a liquid-type cell: gas rows skip it)
+    real_t rE0 = K.rho0;
+    if (any_lane(liquid)) rE0 = liquid ? K.rho0 * exp(-K.a * (yc - y0c)) : K.rho0;
     const real_t e1c = aE * rE0;
     r.aE = aE;
 

@@ -698,6 +698,28 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
     }
 }
 
+// The free-surface integral alone (the same fixed-point terms as reduce_kernel, so the same sums):
+// the adjoint's view of a given state.  Thread = column, blockIdx.y = block of H rows; S must be
+// zero on entry.
+__global__ __launch_bounds__(64) void colsum_kernel(const double *__restrict__ Q, const uint8_t *__restrict__ solid,
+                                                     long long *S, double fix_scale, Consts K, int H)
+{
+    const int i = (int)blockIdx.x * 64 + threadIdx.x;
+    if (i >= K.nx) return;
+    const size_t plane = (size_t)K.nx * K.ny;
+    const int ja = (int)blockIdx.y * H, je = min(K.ny, ja + H);
+    long long colfix = 0;
+#pragma unroll 8
+    for (int j = ja; j < je; ++j) {
+        const size_t cidx = (size_t)j * K.nx + i;
+        const bool fluid = !solid || solid[cidx] == 0;
+        const double q[4] = {0.0, 0.0, 0.0, Q[3 * plane + cidx]};
+        const long long term = __double2ll_rn(detector_term(K, q) * fix_scale);
+        colfix += fluid ? term : 0ll;
+    }
+    if (colfix != 0) atomicAdd((unsigned long long *)&S[i], (unsigned long long)colfix);
+}
+
 // dt = CFL / max rate of the current state, for the host (bn_compute_dt, bn_get_time).
 __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K)
 {
