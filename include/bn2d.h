@@ -139,25 +139,28 @@ const char *bn_strerror(int code);
  * that receives the model-parameter gradient (d Q^{n+1} / d y_L)^T lam_next_dev of the columns'
  * bottom heights y_L (bn_set_bottom; e.g. an obstacle's height): y_L enters the step only through
  * its column's free surface, dy0/dy_L = 1 - a of the column's first fluid cell (0 for a fully solid
- * column).  The library allocates its scratch (about 77 doubles per cell) on the first call and keeps
+ * column).  src_dev: NULL, or a caller-owned device buffer in the state layout added to the result
+ * (lam_dev = (d Q^{n+1} / d Q^n)^T lam_next_dev + src_dev): the per-step term dJ/dQ^n of a loss summed
+ * over a trajectory, so that a reverse sweep needs no separate addition; it may be lam_next_dev
+ * itself but must not overlap lam_dev.  The library allocates its scratch (about 38 doubles per cell) on the first call and keeps
  * it until bn_destroy.  Asynchronous on the context's stream.  Errors: BN_EINVAL (null pointer, dt <= 0
  * or not finite), BN_ENOMEM, BN_EHIP.  A non-physical q_dev gives non-finite values. */
 int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
-                    double *grad_bottom_dev);
+                    double *grad_bottom_dev, const double *src_dev);
 
 /* bn_adjoint_step without any allocation, for callers that cannot allocate device memory (code
  * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments, result
  * and errors as bn_adjoint_step (bitwise the same lambda: the same kernels), but the scratch is a
  * fixed library array of 2^24 doubles (128 MiB) per GPU, reserved when the library's device code is
  * loaded and held until the process ends, instead of memory allocated on the first call.  The grid
- * must fit: 77 nx ny + nx (ceil(ny / 32) + 1) + 2 <= 2^24 (about 217 000 cells, e.g. 512 x 256 or
- * 640 x 320), else BN_EINVAL before any work is enqueued.  The first call on a device resolves the
+ * must fit: 38 nx ny + nx (ceil(ny / 32) + ceil(ny / 16)) <= 2^24 (about 440 000 cells, e.g. 512 x 256
+ * or 768 x 512), else BN_EINVAL before any work is enqueued.  The first call on a device resolves the
  * array's address on that device (the current device must be the context's).  Every call on a GPU
  * uses that GPU's one array: calls that overlap in time on one GPU (other streams, other contexts,
  * other threads) race and give wrong results; calls ordered on one stream, or synchronised, do not.
  * Calls no hipMalloc, hipFree or allocating library routine. */
 int bn_adjoint_step_noalloc(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
-                            double *grad_bottom_dev);
+                            double *grad_bottom_dev, const double *src_dev);
 
 /* ---- Batches: many grids advanced by one launch per step -------------------------------------
  * A batch holds `count` independent grids (members) of any sizes, parameters and masks, e.g. an

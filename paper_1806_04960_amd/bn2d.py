@@ -66,8 +66,8 @@ def lib():
         L.bn_destroy.argtypes = [vp]
         L.bn_destroy.restype = None
         L.bn_set_bottom.argtypes = [vp, dp]
-        L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
-        L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+        L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp]
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
         i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
@@ -119,6 +119,9 @@ class Simulation:
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP library needs a GPU")
         self.nx, self.ny = int(scenario.nx), int(scenario.ny)
+        self._scenario = scenario
+        self._bottom = getattr(scenario, "bottom", None)
+        self._twin = None
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         solid = None
         self._solid_keep = None
@@ -137,6 +140,9 @@ class Simulation:
     def set_bottom(self, bottom):
         """Bottom height of each column for the free-surface detector (nx values; None resets)."""
         import numpy as np
+        self._bottom = None if bottom is None else np.array(bottom, dtype=np.float64)
+        if self._twin is not None:
+            self._twin.set_bottom(bottom)
         if bottom is None:
             check(lib().bn_set_bottom(self._ctx, None), "bn_set_bottom")
             return
@@ -172,25 +178,25 @@ class Simulation:
     def run(self, n_steps: int):
         check(lib().bn_run(self._ctx, int(n_steps)), "bn_run")
 
-    def adjoint_step(self, q, lam_next, dt: float, out=None, grad_bottom=None):
-        """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} for the step of length dt from state q
-        (``bn_adjoint_step``).  q, lam_next: contiguous float64 CUDA tensors [4, ny, nx].  With
+    def adjoint_step(self, q, lam_next, dt: float, out=None, grad_bottom=None, src=None):
+        """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} (+ src) for the step of length dt from state q
+        (``bn_adjoint_step``).  q, lam_next, src: contiguous float64 CUDA tensors [4, ny, nx].  With
         ``grad_bottom`` (a float64 CUDA tensor [nx]) also (dQ^{n+1}/dy_L)^T lambda^{n+1} of the
         columns' bottom heights."""
-        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out, grad_bottom)
+        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out, grad_bottom, src)
 
-    def adjoint_step_noalloc(self, q, lam_next, dt: float, out, grad_bottom=None):
+    def adjoint_step_noalloc(self, q, lam_next, dt: float, out, grad_bottom=None, src=None):
         """The same adjoint through ``bn_adjoint_step_noalloc``: the library's fixed scratch array,
         no allocation (the caller passes ``out``)."""
         return self._adjoint(lib().bn_adjoint_step_noalloc, "bn_adjoint_step_noalloc", q, lam_next, dt, out,
-                             grad_bottom)
+                             grad_bottom, src)
 
-    def _adjoint(self, fn, name, q, lam_next, dt, out, grad_bottom):
+    def _adjoint(self, fn, name, q, lam_next, dt, out, grad_bottom, src=None):
         import torch
         shape = (4, self.ny, self.nx)
         if out is None:
             out = torch.empty(shape, dtype=torch.float64, device="cuda")
-        for arg, t in (("q", q), ("lam_next", lam_next), ("out", out)):
+        for arg, t in (("q", q), ("lam_next", lam_next), ("out", out)) + ((("src", src),) if src is not None else ()):
             if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
                 raise ValueError(f"{arg} must be a contiguous float64 CUDA tensor of shape {shape}")
         gb = None
@@ -199,8 +205,9 @@ class Simulation:
                     and tuple(grad_bottom.shape) == (self.nx,)):
                 raise ValueError(f"grad_bottom must be a contiguous float64 CUDA tensor of shape ({self.nx},)")
             gb = ctypes.c_void_p(grad_bottom.data_ptr())
+        sp = None if src is None else ctypes.c_void_p(src.data_ptr())
         check(fn(self._ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(lam_next.data_ptr()), float(dt),
-                 ctypes.c_void_p(out.data_ptr()), gb), name)
+                 ctypes.c_void_p(out.data_ptr()), gb, sp), name)
         return out
 
     def time(self):
@@ -227,7 +234,23 @@ class Simulation:
         check(lib().bn_get_launch(self._ctx, ctypes.byref(r), ctypes.byref(w)), "bn_get_launch")
         return r.value, w.value
 
+    def twin(self):
+        """A second context of the same grid, model and bottoms on a stream of its own (kept with
+        this one): trajectory gradients recompute their segments on it while this context's stream
+        runs the adjoint steps."""
+        import torch
+        if self._twin is None:
+            t = Simulation(self._scenario, stream=torch.cuda.Stream(), rows_per_block=self.launch()[0],
+                           wavefronts=self.launch()[1])
+            if self._bottom is not None:
+                t.set_bottom(self._bottom)
+            self._twin = t
+        return self._twin
+
     def close(self):
+        if getattr(self, "_twin", None) is not None:
+            self._twin.close()
+            self._twin = None
         if getattr(self, "_ctx", None):
             lib().bn_destroy(self._ctx)
             self._ctx = None
@@ -389,24 +412,47 @@ def _trajectory_forward(sim, q0, dt: float, N: int, w, seg: int, with_loss: bool
 
 def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
     """dJ/dq0 from the checkpoints: each segment, last first, recomputed and reversed (and, into
-    ``gbot`` if given, the sum over the steps of the bottom heights' adjoints)."""
+    ``gbot`` if given, the sum over the steps of the bottom heights' adjoints).  The segments are
+    recomputed on the context's twin, on a stream of its own, one segment ahead of the reverse sweep
+    on the context's stream: segment c - 1 is recomputed while segment c is reversed (two sets of
+    state buffers; events order a set's reuse after the sweep that reads it)."""
     import torch
 
-    lam = torch.zeros_like(ck[0])
+    twin = sim.twin()
+    sa, sb = sim._stream, twin._stream
+    lam = w.clone() if N > 0 else torch.zeros_like(w)  # dJ/dQ^N
     # one row of bottom adjoints per step, summed once at the end
     gsteps = None if gbot is None else torch.empty((N, gbot.numel()), dtype=gbot.dtype, device=gbot.device)
-    buf = [None] * seg
-    for c in range(len(ck) - 1, -1, -1):
+    C = len(ck)
+    sizes = [min(seg, N - c * seg) for c in range(C)]
+    bufs = [[torch.empty_like(ck[0]) for _ in range(max(seg - 1, 0))] for _ in range(2)]
+    ev_rec = [torch.cuda.Event() for _ in range(C)]
+    ev_rev = [torch.cuda.Event() for _ in range(C)]
+    # (the checkpoints and weights were written on the context's stream)
+    sb.wait_stream(sa)
+
+    def recompute(c):
+        twin.set_state(ck[c])
+        for k in range(1, sizes[c]):
+            twin.step(dt)
+            twin.get_state(out=bufs[c % 2][k - 1])
+        ev_rec[c].record(sb)
+
+    recompute(C - 1)
+    for c in range(C - 1, -1, -1):
+        if c >= 1:
+            if c + 1 < C:
+                sb.wait_event(ev_rev[c + 1])  # set (c - 1) % 2 was read by the sweep of segment c + 1
+            recompute(c - 1)
+        sa.wait_event(ev_rec[c])
         n0 = c * seg
-        m = min(seg, N - n0)
-        sim.set_state(ck[c])
-        buf[0] = ck[c]
-        for k in range(1, m):
-            sim.step(dt)
-            buf[k] = sim.get_state()
-        for k in range(m - 1, -1, -1):
-            lam = lam + w  # dJ/dQ^{n0+k+1}
-            lam = sim.adjoint_step(buf[k], lam, dt, grad_bottom=None if gsteps is None else gsteps[n0 + k])
+        for k in range(sizes[c] - 1, -1, -1):
+            q = ck[c] if k == 0 else bufs[c % 2][k - 1]
+            # lam = dJ/dQ^{n0+k+1} in; out dJ/dQ^{n0+k}, with that step's own term w added (none for q0)
+            lam = sim.adjoint_step(q, lam, dt, grad_bottom=None if gsteps is None else gsteps[n0 + k],
+                                   src=w if n0 + k > 0 else None)
+        ev_rev[c].record(sa)
+    sa.wait_stream(sb)
     if gbot is not None and N > 0:
         gbot += gsteps.sum(dim=0)
     sim.set_state(ck[0])
@@ -461,10 +507,11 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
                     J += (w * q).sum()
                 if k + 1 < N:
                     states.append(q)
-        lam = torch.zeros_like(states[0])
+        lam = w.clone() if N > 0 else torch.zeros_like(w)  # dJ/dQ^N
         gsteps = torch.empty((N, sim.nx), dtype=torch.float64, device=q0.device) if bottom else None
         for n in range(N - 1, -1, -1):
-            lam = sim.adjoint_step(states[n], lam + w, dt, grad_bottom=None if gsteps is None else gsteps[n])
+            lam = sim.adjoint_step(states[n], lam, dt, grad_bottom=None if gsteps is None else gsteps[n],
+                                   src=w if n > 0 else None)
         if bottom and N > 0:
             gbot += gsteps.sum(dim=0)
         sim.set_state(states[0])

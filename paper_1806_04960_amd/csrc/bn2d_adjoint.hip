@@ -8,27 +8,27 @@
 //   D-+(e)      = edge_x / edge_y of the two edge states of e (a wall or solid side mirrors the
 //                 fluid side's state)
 //   Q^{n+1}_c   = Q^n_c - dt/dx (D+_W + D-_E + fdiff) - dt/dy (D+_S + D-_N + gdiff) - dt vol
-// is reversed in five passes, one thread per cell, edge or column, through library-owned planes:
-//   1. adj_rec_kernel     recompute Rec_c (the edge states the edges need), 21 planes
-//   2. adj_edge_kernel    per x- and y-edge (one launch for both kinds): recompute D-+, reverse
-//                         it with the adjoints of the two cells' updates, and write the adjoints
-//                         of the edge states to their owners (each edge state feeds exactly one
-//                         edge: no accumulation), 18 planes
-//   3. adj_cell_kernel    reverse the reconstruction: adjoints of the 3 x 3 stencil (36 planes;
-//                         a first-order cell reaches only itself and writes only that entry and a
-//                         0 in the second-order flag plane) and of y0_i (1 plane)
-//   4. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
+// is reversed in three launches through library-owned planes:
+//   1. adj_fused_kernel   per tile of 64 x 4 cells: recompute Rec of the tile and its one-cell halo
+//                         into LDS, reverse every x- and y-edge touching the tile (recompute D-+ and
+//                         reverse it with the adjoints of the two cells' updates; the adjoints of
+//                         the tile cells' edge states go back into LDS: each edge state feeds exactly
+//                         one edge, no accumulation), then reverse each tile cell's reconstruction:
+//                         adjoints of its 3 x 3 stencil (36 planes; a first-order cell reaches only
+//                         itself and writes only that entry and a 0 in the second-order flag plane)
+//                         and of y0_i (1 plane)
+//   2. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
 //                         gather adds the blocks' partial sums in order: deterministic)
-//   5. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
+//   3. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
 //                         fluid cells whose stencil holds c (of a first-order neighbour only
-//                         c's own entry) + the detector's dy/(alpha_l -
-//                         alpha_g) times its column's y0 adjoint (alpha only; (dy - d)/(alpha_l -
-//                         alpha_g) in the first fluid cell of a column whose bottom lies d off the
-//                         grid); solid cells pass lambda through (their state is copied and never
-//                         read)
-//                         and (if asked) the adjoint of each column's bottom height: its y0
-//                         adjoint times dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g),
-//                         written by the column's first fluid cell
+//                         c's own entry) + the detector's dy/(alpha_l - alpha_g) times its column's
+//                         y0 adjoint (alpha only; (dy - d)/(alpha_l - alpha_g) in the first fluid
+//                         cell of a column whose bottom lies d off the grid); solid cells pass
+//                         lambda through (their state is copied and never read); and (if asked) the
+//                         adjoint of each column's bottom height: its y0 adjoint times dy0/dy_L =
+//                         (alpha_l - alpha_first) / (alpha_l - alpha_g), written by the column's
+//                         first fluid cell; an optional source (e.g. dJ/dQ^n of a trajectory loss) is
+//                         added to lambda^n last
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,25 +44,24 @@ struct AdjArgs {
     const uint8_t *solid;   // nx*ny or null
     const int *jb;          // first fluid row per column
     const double *dbot;     // per column: bottom height minus the top of its solid run, or null
-    const long long *S;     // fixed-point free-surface integral of Q^n per column
+    const long long *Sp;    // fixed-point free-surface integral of Q^n per column: nSp partials [nSp][nx]
+    int nSp;
     double fix_inv;
     double dt, dtdx, dtdy;
-    double *rec;            // kRecPlanes planes
-    double *fb;             // kFacePlanes planes
     double *wb;             // 36 planes (a first-order cell writes only its own entry, (1, 1))
     double *y0b;            // 1 plane (0 for solid cells)
     double *sob;            // 1 plane: 1 where the fluid cell's reconstruction is second order
     double *colb;           // [ceil(ny / kColRows)][nx] partial column sums
     double *gbot;           // [nx] adjoint of the bottom heights, or null
+    const double *src;      // 4 planes added to lambda^n, or null
 };
 
 constexpr int kColRows = 32;
 
-// plane layout of rec: qW 0-3, qE 4-7, qS 8-11, qN 12-15, e1S 16, e1N 17, aE 18, yS 19, yN 20
-// (the heights of the S/N states: the edge's for a second-order cell, the centre's for a
-// first-order one); fb: the adjoints of the first 18
+// record planes of the fused pass's LDS: qW 0-3, qE 4-7, qS 8-11, qN 12-15, e1S 16, e1N 17, aE 18,
+// yS 19, yN 20 (the heights of the S/N states: the edge's for a second-order cell, the centre's for a
+// first-order one); the face adjoints take the first 18 of them afterwards
 constexpr int kRecPlanes = 21;
-constexpr int kFacePlanes = 18;
 enum : int { P_QW = 0, P_QE = 4, P_QS = 8, P_QN = 12, P_E1S = 16, P_E1N = 17, P_AE = 18, P_YS = 19, P_YN = 20 };
 
 __device__ __forceinline__ bool fluid_at(const AdjArgs &a, int i, int j)
@@ -85,7 +84,9 @@ __device__ __forceinline__ double first_gap(const AdjArgs &a, int i)
 
 __device__ __forceinline__ double y0_of(const AdjArgs &a, int i)
 {
-    double v = (a.K.ylo + a.jb[i] * a.K.dy) + a.K.dy * ((double)a.S[i] * a.fix_inv);
+    long long S = 0;
+    for (int b = 0; b < a.nSp; ++b) S += a.Sp[(size_t)b * a.K.nx + i];  // exact: the order does not matter
+    double v = (a.K.ylo + a.jb[i] * a.K.dy) + a.K.dy * ((double)S * a.fix_inv);
     if (a.dbot && a.jb[i] < a.K.ny) v += a.dbot[i] * first_gap(a, i);
     return v;
 }
@@ -116,103 +117,80 @@ struct ArrayStencil {
     __device__ __forceinline__ int f(int dj, int di) const { return wf[dj][di]; }
 };
 
-__global__ __launch_bounds__(256) void adj_rec_kernel(AdjArgs a)
-{
-    const size_t n = (size_t)a.K.nx * a.K.ny;
-    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int i = (int)(c % a.K.nx), j = (int)(c / a.K.nx);
-    if (!fluid_at(a, i, j)) return;
-    double wq[3][3][4];
-    int wf[3][3];
-    load_stencil(a, i, j, wq, wf);
-    Rec r;
-    ArrayStencil st{wq, wf};
-    reconstruct(a.K, st, j, y0_of(a, i), a.dt, r);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        a.rec[(P_QW + k) * n + c] = r.qW[k];
-        a.rec[(P_QE + k) * n + c] = r.qE[k];
-        a.rec[(P_QS + k) * n + c] = r.qS[k];
-        a.rec[(P_QN + k) * n + c] = r.qN[k];
-    }
-    a.rec[P_E1S * n + c] = r.e1S;
-    a.rec[P_E1N * n + c] = r.e1N;
-    a.rec[P_AE * n + c] = r.aE;
-    a.rec[P_YS * n + c] = r.yS;
-    a.rec[P_YN * n + c] = r.yN;
-}
+// ---- pass 1: reconstruction, edges and cells, fused over 64 x 4 tiles ----------------------------
+// One workgroup (256 threads) per tile of 64 columns x 4 rows.  (a) It recomputes the reconstruction
+// of the tile's cells and of a one-cell halo around it (66 x 6 cells) into LDS; (b) every x- and y-edge
+// touching a tile cell (65 x 4 and 64 x 5) is reversed from those records and the lambdas of its two
+// cells, the adjoints of the tile cells' edge states going back into LDS (over the records, after a
+// barrier); (c) each tile cell reverses its reconstruction.  The edge-state records and their
+// adjoints never reach HBM.
+constexpr int kTX = 64, kTY = 4, kHX = kTX + 2, kHY = kTY + 2, kHalo = kHX * kHY;  // 396 records
 
-// x-edge e (between cells e-1 and e of row j), e = 0..nx; t = j (nx+1) + e.
-__device__ __forceinline__ void adj_xedge(const AdjArgs &a, long long t)
+// x-edge between local columns e-1 and e (e = 0..64) of tile row ty; qmb/qpb: the adjoints of the
+// left cell's east state and of the right cell's west state (a missing side mirrors the fluid one,
+// so its share is folded into the fluid side's)
+__device__ __forceinline__ void fused_xedge(const AdjArgs &a, const double (*sr)[kHalo], int i0, int j0, int e, int ty,
+                                            double qmb[4], double qpb[4], bool &flL, bool &flR)
 {
-    const int ne = a.K.nx + 1;
-    if (t >= (long long)ne * a.K.ny) return;
-    const int e = (int)(t % ne), j = (int)(t / ne);
-    const int iL = e - 1, iR = e;
-    const bool flL = fluid_at(a, iL, j), flR = fluid_at(a, iR, j);
+    const int iL = i0 + e - 1, iR = i0 + e, j = j0 + ty;
+    flL = fluid_at(a, iL, j);
+    flR = fluid_at(a, iR, j);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qmb[k] = qpb[k] = 0.0;
     if (!flL && !flR) return;
     const int fL = flags_at(a, iL, j), fR = flags_at(a, iR, j);
+    const int hL = (ty + 1) * kHX + e, hR = hL + 1;  // halo-record indices of the two cells
     const size_t n = (size_t)a.K.nx * a.K.ny;
-    const size_t cL = flL ? (size_t)j * a.K.nx + iL : 0, cR = flR ? (size_t)j * a.K.nx + iR : 0;
-    double qEL[4], qWR[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        qEL[k] = flL ? a.rec[(P_QE + k) * n + cL] : 0.0;
-        qWR[k] = flR ? a.rec[(P_QW + k) * n + cR] : 0.0;
-    }
-    // the edge's states: a missing side mirrors the other (normal momentum negated unless the
-    // side is transmissive)
-    const double sL = (!flL && !(fL & F_TX)) ? -1.0 : 1.0, sR = (!flR && !(fR & F_TX)) ? -1.0 : 1.0;
     double qm[4], qp[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        qm[k] = flL ? qEL[k] : qWR[k];
-        qp[k] = flR ? qWR[k] : qEL[k];
+        const double qEL = flL ? sr[P_QE + k][hL] : 0.0, qWR = flR ? sr[P_QW + k][hR] : 0.0;
+        qm[k] = flL ? qEL : qWR;
+        qp[k] = flR ? qWR : qEL;
     }
+    const double sL = (!flL && !(fL & F_TX)) ? -1.0 : 1.0, sR = (!flR && !(fR & F_TX)) ? -1.0 : 1.0;
     qm[1] *= sL;
     qp[1] *= sR;
+    const size_t cL = flL ? (size_t)j * a.K.nx + iL : 0, cR = flR ? (size_t)j * a.K.nx + iR : 0;
     double Dmb[4], Dpb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Dmb[k] = flL ? -a.dtdx * a.lam1[k * n + cL] : 0.0;  // D- of this edge enters cell L (its D-_E)
-        Dpb[k] = flR ? -a.dtdx * a.lam1[k * n + cR] : 0.0;  // D+ enters cell R (its D+_W)
+        Dmb[k] = flL ? -a.dtdx * a.lam1[k * n + cL] : 0.0;
+        Dpb[k] = flR ? -a.dtdx * a.lam1[k * n + cR] : 0.0;
     }
-    double qmb[4] = {0, 0, 0, 0}, qpb[4] = {0, 0, 0, 0};
-    edge_x_rev(a.K, qm, qp, Dmb, Dpb, qmb, qpb);
-    qmb[1] *= sL;
-    qpb[1] *= sR;
-    if (flL) {
+    double bm[4] = {0, 0, 0, 0}, bp[4] = {0, 0, 0, 0};
+    edge_x_rev(a.K, qm, qp, Dmb, Dpb, bm, bp);
+    bm[1] *= sL;
+    bp[1] *= sR;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a.fb[(P_QE + k) * n + cL] = qmb[k] + (flR ? 0.0 : qpb[k]);
-    }
-    if (flR) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a.fb[(P_QW + k) * n + cR] = qpb[k] + (flL ? 0.0 : qmb[k]);
+    for (int k = 0; k < 4; ++k) {
+        qmb[k] = bm[k] + (flR ? 0.0 : bp[k]);
+        qpb[k] = bp[k] + (flL ? 0.0 : bm[k]);
     }
 }
 
-// y-edge e (between rows e-1 and e of column i), e = 0..ny; t = e nx + i.
-__device__ __forceinline__ void adj_yedge(const AdjArgs &a, long long t)
+// y-edge between local rows e-1 and e (e = 0..4) of tile column tx
+__device__ __forceinline__ void fused_yedge(const AdjArgs &a, const double (*sr)[kHalo], int i0, int j0, int tx, int e,
+                                            double qmb[5], double qpb[5], bool &flB, bool &flT)
 {
-    const int nx = a.K.nx;
-    if (t >= (long long)nx * (a.K.ny + 1)) return;
-    const int i = (int)(t % nx), e = (int)(t / nx);
-    const int jB = e - 1, jT = e;
-    const bool flB = fluid_at(a, i, jB), flT = fluid_at(a, i, jT);
+    const int i = i0 + tx, jB = j0 + e - 1, jT = j0 + e;
+    flB = fluid_at(a, i, jB);
+    flT = fluid_at(a, i, jT);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qmb[k] = qpb[k] = 0.0;
     if (!flB && !flT) return;
     const int fB = flags_at(a, i, jB), fT = flags_at(a, i, jT);
-    const size_t n = (size_t)nx * a.K.ny;
-    const size_t cB = flB ? (size_t)jB * nx + i : 0, cT = flT ? (size_t)jT * nx + i : 0;
+    const int hB = e * kHX + tx + 1, hT = hB + kHX;
+    const size_t n = (size_t)a.K.nx * a.K.ny;
     double qNB[4], qST[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        qNB[k] = flB ? a.rec[(P_QN + k) * n + cB] : 0.0;
-        qST[k] = flT ? a.rec[(P_QS + k) * n + cT] : 0.0;
+        qNB[k] = flB ? sr[P_QN + k][hB] : 0.0;
+        qST[k] = flT ? sr[P_QS + k][hT] : 0.0;
     }
-    const double e1NB = flB ? a.rec[P_E1N * n + cB] : 0.0, e1ST = flT ? a.rec[P_E1S * n + cT] : 0.0;
-    const double aEB = flB ? a.rec[P_AE * n + cB] : 0.0, aET = flT ? a.rec[P_AE * n + cT] : 0.0;
-    const double yN = flB ? a.rec[P_YN * n + cB] : 0.0, yS = flT ? a.rec[P_YS * n + cT] : 0.0;
+    const double e1NB = flB ? sr[P_E1N][hB] : 0.0, e1ST = flT ? sr[P_E1S][hT] : 0.0;
+    const double aEB = flB ? sr[P_AE][hB] : 0.0, aET = flT ? sr[P_AE][hT] : 0.0;
+    const double yN = flB ? sr[P_YN][hB] : 0.0, yS = flT ? sr[P_YS][hT] : 0.0;
     const double sB = (!flB && !(fB & F_TY)) ? -1.0 : 1.0, sT = (!flT && !(fT & F_TY)) ? -1.0 : 1.0;
     double qm[4], qp[4];
 #pragma unroll
@@ -224,45 +202,112 @@ __device__ __forceinline__ void adj_yedge(const AdjArgs &a, long long t)
     qp[2] *= sT;
     const double e1m = flB ? e1NB : e1ST, aEm = flB ? aEB : aET, ym = flB ? yN : yS;
     const double e1p = flT ? e1ST : e1NB, aEp = flT ? aET : aEB, yp = flT ? yS : yN;
+    const size_t cB = flB ? (size_t)jB * a.K.nx + i : 0, cT = flT ? (size_t)jT * a.K.nx + i : 0;
     double Dmb[4], Dpb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Dmb[k] = flB ? -a.dtdy * a.lam1[k * n + cB] : 0.0;  // D- enters the cell below (its D-_N)
-        Dpb[k] = flT ? -a.dtdy * a.lam1[k * n + cT] : 0.0;  // D+ enters the cell above (its D+_S)
+        Dmb[k] = flB ? -a.dtdy * a.lam1[k * n + cB] : 0.0;
+        Dpb[k] = flT ? -a.dtdy * a.lam1[k * n + cT] : 0.0;
     }
-    double qmb[4] = {0, 0, 0, 0}, qpb[4] = {0, 0, 0, 0}, e1mb = 0.0, e1pb = 0.0;
-    edge_y_rev(a.K, qm, e1m, aEm, ym, qp, e1p, aEp, yp, Dmb, Dpb, qmb, e1mb, qpb, e1pb);
-    qmb[2] *= sB;
-    qpb[2] *= sT;
-    if (flB) {
+    double bm[4] = {0, 0, 0, 0}, bp[4] = {0, 0, 0, 0}, e1mb = 0.0, e1pb = 0.0;
+    edge_y_rev(a.K, qm, e1m, aEm, ym, qp, e1p, aEp, yp, Dmb, Dpb, bm, e1mb, bp, e1pb);
+    bm[2] *= sB;
+    bp[2] *= sT;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a.fb[(P_QN + k) * n + cB] = qmb[k] + (flT ? 0.0 : qpb[k]);
-        a.fb[P_E1N * n + cB] = e1mb + (flT ? 0.0 : e1pb);
+    for (int k = 0; k < 4; ++k) {
+        qmb[k] = bm[k] + (flT ? 0.0 : bp[k]);
+        qpb[k] = bp[k] + (flB ? 0.0 : bm[k]);
     }
-    if (flT) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a.fb[(P_QS + k) * n + cT] = qpb[k] + (flB ? 0.0 : qmb[k]);
-        a.fb[P_E1S * n + cT] = e1pb + (flB ? 0.0 : e1mb);
-    }
+    qmb[4] = e1mb + (flT ? 0.0 : e1pb);
+    qpb[4] = e1pb + (flB ? 0.0 : e1mb);
 }
 
-// Both edge passes in one launch (they read the same reconstruction planes and write disjoint
-// adjoint planes): the first nbx workgroups take the x-edges, the rest the y-edges, so that the two
-// halves fill the GPU together instead of one after the other.
-__global__ __launch_bounds__(64) void adj_edge_kernel(AdjArgs a, unsigned nbx)
+__global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
 {
-    if (blockIdx.x < nbx)
-        adj_xedge(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
-    else
-        adj_yedge(a, (long long)(blockIdx.x - nbx) * blockDim.x + threadIdx.x);
-}
+    __shared__ double sr[kRecPlanes][kHalo];  // records, then (planes 0..17, first 256 entries) face adjoints
+    __shared__ double sy0[kHX];               // free-surface heights of the tile's columns and halo
+    const int t = threadIdx.x;
+    const int i0 = (int)blockIdx.x * kTX, j0 = (int)blockIdx.y * kTY;
+    if (t < kHX && i0 + t - 1 >= 0 && i0 + t - 1 < a.K.nx) sy0[t] = y0_of(a, i0 + t - 1);
+    __syncthreads();
 
-__global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
-{
+    // (a) records of the tile and its halo
+    for (int h = t; h < kHalo; h += 256) {
+        const int i = i0 + h % kHX - 1, j = j0 + h / kHX - 1;
+        if (!fluid_at(a, i, j)) continue;
+        double wq[3][3][4];
+        int wf[3][3];
+        load_stencil(a, i, j, wq, wf);
+        Rec r;
+        ArrayStencil st{wq, wf};
+        reconstruct(a.K, st, j, sy0[h % kHX], a.dt, r);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sr[P_QW + k][h] = r.qW[k];
+            sr[P_QE + k][h] = r.qE[k];
+            sr[P_QS + k][h] = r.qS[k];
+            sr[P_QN + k][h] = r.qN[k];
+        }
+        sr[P_E1S][h] = r.e1S;
+        sr[P_E1N][h] = r.e1N;
+        sr[P_AE][h] = r.aE;
+        sr[P_YS][h] = r.yS;
+        sr[P_YN][h] = r.yN;
+    }
+    __syncthreads();
+
+    // (b) edges: thread t takes x-edges t and t + 256 (of 65 x 4) and y-edges t and t + 256 (of 64 x 5)
+    constexpr int nX = (kTX + 1) * kTY, nY = kTX * (kTY + 1);
+    double xm[2][4], xp[2][4], ym[2][5], yp[2][5];
+    bool xl[2], xr[2], yb[2], yt[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int ex = t + 256 * u;
+        xl[u] = xr[u] = false;
+        if (ex < nX) fused_xedge(a, sr, i0, j0, ex % (kTX + 1), ex / (kTX + 1), xm[u], xp[u], xl[u], xr[u]);
+        const int ey = t + 256 * u;
+        yb[u] = yt[u] = false;
+        if (ey < nY) fused_yedge(a, sr, i0, j0, ey % kTX, ey / kTX, ym[u], yp[u], yb[u], yt[u]);
+    }
+    __syncthreads();  // every record read: the face adjoints go over them
+    // face adjoint of tile cell c = ty * 64 + tx in sr[plane][c]; a cell outside the tile or not
+    // fluid is skipped (a missing side's share is already in its fluid neighbour's)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int ex = t + 256 * u;
+        if (ex < nX) {
+            const int e = ex % (kTX + 1), ty = ex / (kTX + 1);
+            if (xl[u] && e >= 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sr[P_QE + k][ty * kTX + e - 1] = xm[u][k];
+            }
+            if (xr[u] && e < kTX) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sr[P_QW + k][ty * kTX + e] = xp[u][k];
+            }
+        }
+        const int ey = t + 256 * u;
+        if (ey < nY) {
+            const int tx = ey % kTX, e = ey / kTX;
+            if (yb[u] && e >= 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sr[P_QN + k][(e - 1) * kTX + tx] = ym[u][k];
+                sr[P_E1N][(e - 1) * kTX + tx] = ym[u][4];
+            }
+            if (yt[u] && e < kTY) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sr[P_QS + k][e * kTX + tx] = yp[u][k];
+                sr[P_E1S][e * kTX + tx] = yp[u][4];
+            }
+        }
+    }
+    __syncthreads();
+
+    // (c) the tile cell's reconstruction reversed
+    const int i = i0 + (t % kTX), j = j0 + t / kTX;
+    if (i >= a.K.nx || j >= a.K.ny) return;
     const size_t n = (size_t)a.K.nx * a.K.ny;
-    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int i = (int)(c % a.K.nx), j = (int)(c / a.K.nx);
+    const size_t c = (size_t)j * a.K.nx + i;
     if (!fluid_at(a, i, j)) {
         a.y0b[c] = 0.0;
         return;
@@ -270,8 +315,6 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
     double wq[3][3][4];
     int wf[3][3];
     load_stencil(a, i, j, wq, wf);
-    // the reconstruction's second-order switch (as reconstruct_rev takes it): a first-order cell's
-    // reverse reaches only the cell itself, so only that entry of its stencil adjoint is stored
     bool so = wq[1][1][3] > a.K.so_thr;
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
@@ -281,16 +324,16 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
     RecBar rb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        rb.qW[k] = a.fb[(P_QW + k) * n + c];
-        rb.qE[k] = a.fb[(P_QE + k) * n + c];
-        rb.qS[k] = a.fb[(P_QS + k) * n + c];
-        rb.qN[k] = a.fb[(P_QN + k) * n + c];
+        rb.qW[k] = sr[P_QW + k][t];
+        rb.qE[k] = sr[P_QE + k][t];
+        rb.qS[k] = sr[P_QS + k][t];
+        rb.qN[k] = sr[P_QN + k][t];
         const double l = a.lam1[k * n + c];
         rb.fdiff[k] = -a.dtdx * l;
         rb.gdiff[k] = -a.dtdy * l;
     }
-    rb.e1S = a.fb[P_E1S * n + c];
-    rb.e1N = a.fb[P_E1N * n + c];
+    rb.e1S = sr[P_E1S][t];
+    rb.e1N = sr[P_E1N][t];
     rb.vol2 = -a.dt * a.lam1[2 * n + c];
     rb.vol3 = -a.dt * a.lam1[3 * n + c];
     double wqb[3][3][4];
@@ -300,7 +343,7 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
         for (int di = 0; di < 3; ++di)
 #pragma unroll
             for (int k = 0; k < 4; ++k) wqb[dj][di][k] = 0.0;
-    const double yb = reconstruct_rev(a.K, wq, wf, j, y0_of(a, i), a.dt, rb, wqb);
+    const double ybar = reconstruct_rev(a.K, wq, wf, j, sy0[(t % kTX) + 1], a.dt, rb, wqb);
     if (so) {
 #pragma unroll
         for (int dj = 0; dj < 3; ++dj)
@@ -313,7 +356,7 @@ __global__ __launch_bounds__(64) void adj_cell_kernel(AdjArgs a)
         for (int k = 0; k < 4; ++k) a.wb[((1 * 3 + 1) * 4 + k) * n + c] = wqb[1][1][k];
     }
     a.sob[c] = so ? 1.0 : 0.0;
-    a.y0b[c] = yb;
+    a.y0b[c] = ybar;
 }
 
 // partial sum of rows [kColRows y, kColRows (y+1)) of column i (grid: columns / 64 x row blocks)
@@ -340,6 +383,11 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
     double out[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[k] = a.lam1[k * n + c];
+    double add[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.src) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) add[k] = a.src[k * n + c];
+    }
     if (fluid_at(a, i, j)) {
         // stencil entry (dj, di) of the cell (i - di + 1, j - dj + 1) is this cell
 #pragma unroll
@@ -365,14 +413,14 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
         a.gbot[i] = 0.0;  // a column without fluid cells
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k];
+    for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k] + add[k];
 }
 
 }  // namespace bn
 
 // Launch the passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
 namespace bn {
-constexpr int kAdjPlanes = kRecPlanes + kFacePlanes + 36 + 2;
+constexpr int kAdjPlanes = 36 + 2;
 }
 
 size_t bn_adjoint_scratch(int nx, int ny)
@@ -381,8 +429,9 @@ size_t bn_adjoint_scratch(int nx, int ny)
 }
 
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
-                             const uint8_t *solid, const int *jb, const double *dbot, const long long *S,
-                             double fix_inv, double dt, double *scratch, double *gbot, hipStream_t stream)
+                             const uint8_t *solid, const int *jb, const double *dbot, const long long *Sp,
+                             int nSp, double fix_inv, double dt, double *scratch, double *gbot, const double *src,
+                             hipStream_t stream)
 {
     bn::AdjArgs a;
     a.K = K;
@@ -393,24 +442,21 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.jb = jb;
     a.dbot = dbot;
     a.gbot = gbot;
-    a.S = S;
+    a.src = src;
+    a.Sp = Sp;
+    a.nSp = nSp;
     a.fix_inv = fix_inv;
     a.dt = dt;
     a.dtdx = dt * K.inv_dx;
     a.dtdy = dt * K.inv_dy;
     const size_t n = (size_t)K.nx * K.ny;
-    a.rec = scratch;
-    a.fb = a.rec + bn::kRecPlanes * n;
-    a.wb = a.fb + bn::kFacePlanes * n;
+    a.wb = scratch;
     a.y0b = a.wb + 36 * n;
     a.sob = a.y0b + n;
     a.colb = a.sob + n;
-    const unsigned gc = (unsigned)((n + 255) / 256), gc64 = (unsigned)((n + 63) / 64);
-    hipLaunchKernelGGL(bn::adj_rec_kernel, dim3(gc), dim3(256), 0, stream, a);
-    const size_t nxe = (size_t)(K.nx + 1) * K.ny, nye = (size_t)K.nx * (K.ny + 1);
-    const unsigned nbx = (unsigned)((nxe + 63) / 64), nby = (unsigned)((nye + 63) / 64);
-    hipLaunchKernelGGL(bn::adj_edge_kernel, dim3(nbx + nby), dim3(64), 0, stream, a, nbx);
-    hipLaunchKernelGGL(bn::adj_cell_kernel, dim3(gc64), dim3(64), 0, stream, a);
+    const unsigned gc = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((K.nx + bn::kTX - 1) / bn::kTX, (K.ny + bn::kTY - 1) / bn::kTY),
+                       dim3(256), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
                        0, stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);

@@ -31,8 +31,9 @@ __global__ void y0_kernel(const long long *S, const int *jb, const double *dbot,
 // the discrete adjoint's passes (bn2d_adjoint.hip)
 size_t bn_adjoint_scratch(int nx, int ny);
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
-                             const uint8_t *solid, const int *jb, const double *dbot, const long long *S,
-                             double fix_inv, double dt, double *scratch, double *gbot, hipStream_t stream);
+                             const uint8_t *solid, const int *jb, const double *dbot, const long long *Sp,
+                             int nSp, double fix_inv, double dt, double *scratch, double *gbot, const double *src,
+                             hipStream_t stream);
 
 namespace {
 
@@ -94,7 +95,7 @@ struct Grid {
     double *y0 = nullptr;               // [nx] staging for bn_get_y0
     double *dt = nullptr;               // staging for dt queries
     double *adj = nullptr;              // adjoint scratch planes, allocated on first use
-    long long *adjS = nullptr;          // [nx] free-surface integral of the adjoint's state, + 2 words
+    long long *adjS = nullptr;          // [ceil(ny / 16)][nx] free-surface partial sums of the adjoint's state
     bool has_state = false;
 };
 
@@ -337,15 +338,15 @@ int query_dt(bn_batch *b, Grid &g)
 
 bool bad_member(const bn_batch *b, int32_t k) { return !b || k < 0 || k >= (int32_t)b->g.size(); }
 
-// The fixed-point free-surface integral of a given state into S (nx words, cleared first).
+// The fixed-point free-surface integral of a given state as colsum_blocks(ny) partial sums per
+// column into Sp ([blocks][nx] words, overwritten: no clearing, no atomics).
 constexpr int kColsumRows = 16;
-int adjoint_colsum(bn_batch *b, Grid &g, const double *q_dev, long long *S)
+int colsum_blocks(int ny) { return (ny + kColsumRows - 1) / kColsumRows; }
+int adjoint_colsum(bn_batch *b, Grid &g, const double *q_dev, long long *Sp)
 {
     const int nx = g.grid.nx, ny = g.grid.ny;
-    hipLaunchKernelGGL(bn::zero_kernel, dim3((nx + 255) / 256), dim3(256), 0, b->stream, S, nx);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(bn::colsum_kernel, dim3((nx + 63) / 64, (ny + kColsumRows - 1) / kColsumRows), dim3(64), 0,
-                       b->stream, q_dev, g.solid, S, g.dev.fix_scale, g.dev.K, kColsumRows);
+    hipLaunchKernelGGL(bn::colsum_kernel, dim3((nx + 63) / 64, colsum_blocks(ny)), dim3(64), 0, b->stream, q_dev,
+                       g.solid, Sp, g.dev.fix_scale, g.dev.K, kColsumRows);
     HIP_TRY(hipGetLastError());
     return BN_OK;
 }
@@ -697,7 +698,7 @@ int bn_get_launch(bn_ctx *c, int32_t *rows_per_block, int32_t *wavefronts)
 }
 
 int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
-                    double *grad_bottom_dev)
+                    double *grad_bottom_dev, const double *src_dev)
 {
     if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
     bn_batch *b = c->b;
@@ -705,7 +706,7 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     const int nx = g.grid.nx, ny = g.grid.ny;
     if (!g.adj) {
         hipError_t e = hipMalloc(&g.adj, sizeof(double) * bn_adjoint_scratch(nx, ny));
-        if (e == hipSuccess) e = hipMalloc(&g.adjS, sizeof(long long) * (nx + 2));
+        if (e == hipSuccess) e = hipMalloc(&g.adjS, sizeof(long long) * (size_t)nx * colsum_blocks(ny));
         if (e != hipSuccess) {
             if (g.adj) (void)hipFree(g.adj);
             g.adj = nullptr;
@@ -718,8 +719,8 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
     long long *S = g.adjS;
     const int rc = adjoint_colsum(b, g, q_dev, S);
     if (rc) return rc;
-    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
-                              g.adj, grad_bottom_dev, b->stream));
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, colsum_blocks(ny),
+                              g.dev.fix_inv, dt, g.adj, grad_bottom_dev, src_dev, b->stream));
     return BN_OK;
 }
 
@@ -758,24 +759,24 @@ int scratch_address(double **out)
 extern "C" {
 
 int bn_adjoint_step_noalloc(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
-                            double *grad_bottom_dev)
+                            double *grad_bottom_dev, const double *src_dev)
 {
     if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
     bn_batch *b = c->b;
     Grid &g = b->g[0];
     const int nx = g.grid.nx, ny = g.grid.ny;
-    // the free-surface words (nx integrals, the CFL slot, the flag) follow the adjoint's planes
+    // the free-surface partial sums follow the adjoint's planes
     const size_t planes = bn_adjoint_scratch(nx, ny);
-    if (planes + (size_t)nx + 2 > kNoAllocScratchDoubles) return BN_EINVAL;
+    if (planes + (size_t)nx * colsum_blocks(ny) > kNoAllocScratchDoubles) return BN_EINVAL;
     double *base = nullptr;
     const int rc = scratch_address(&base);
     if (rc) return rc;
     long long *S = reinterpret_cast<long long *>(base + planes);
-    // (the array keeps the previous call's contents: the integrals are cleared first)
+    // (the array keeps the previous call's contents: every word used is written before it is read)
     const int rc2 = adjoint_colsum(b, g, q_dev, S);
     if (rc2) return rc2;
-    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, g.dev.fix_inv, dt,
-                              base, grad_bottom_dev, b->stream));
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, colsum_blocks(ny),
+                              g.dev.fix_inv, dt, base, grad_bottom_dev, src_dev, b->stream));
     return BN_OK;
 }
 

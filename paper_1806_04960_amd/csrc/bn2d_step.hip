@@ -698,11 +698,11 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ Q
     }
 }
 
-// The free-surface integral alone (the same fixed-point terms as reduce_kernel, so the same sums):
-// the adjoint's view of a given state.  Thread = column, blockIdx.y = block of H rows; S must be
-// zero on entry.
+// The free-surface integral alone, in partial sums (the same fixed-point terms as reduce_kernel, so
+// their exact sum is the same integral): the adjoint's view of a given state.  Thread = column,
+// blockIdx.y = block of H rows, whose partial is stored at Sp[blockIdx.y * nx + column].
 __global__ __launch_bounds__(64) void colsum_kernel(const double *__restrict__ Q, const uint8_t *__restrict__ solid,
-                                                     long long *S, double fix_scale, Consts K, int H)
+                                                     long long *Sp, double fix_scale, Consts K, int H)
 {
     const int i = (int)blockIdx.x * 64 + threadIdx.x;
     if (i >= K.nx) return;
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(64) void colsum_kernel(const double *__restrict__ Q
         const long long term = __double2ll_rn(detector_term(K, q) * fix_scale);
         colfix += fluid ? term : 0ll;
     }
-    if (colfix != 0) atomicAdd((unsigned long long *)&S[i], (unsigned long long)colfix);
+    Sp[(size_t)blockIdx.y * K.nx + i] = colfix;
 }
 
 // dt = CFL / max rate of the current state, for the host (bn_compute_dt, bn_get_time).

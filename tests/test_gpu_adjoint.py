@@ -386,3 +386,22 @@ def test_wall_height_gradient_of_the_wall_load_over_40_steps(bn, torch_cuda):
         print(f"{kind}: dJ/dh_w adjoint {g:.8e}, differences {fd2:.8e} (h vs h/2 {spread:.1e}), error {err:.1e}",
               flush=True)
         assert abs(fd2) > 0 and err <= 1e-6 + 2 * spread
+
+
+def test_source_term_is_added_to_the_adjoint(bn, torch_cuda):
+    """bn_adjoint_step's src_dev: the result is the adjoint plus the source, bit for bit (a trajectory's
+    per-step loss term added by the same pass)."""
+    torch = torch_cuda
+    s = sc.generic_state(sc.wall_impact(0, 40, 20), seed=4)
+    rng = np.random.default_rng(2)
+    lam = torch.from_numpy(rng.normal(size=s.q.shape)).cuda()
+    src = torch.from_numpy(rng.normal(size=s.q.shape)).cuda()
+    with bn.Simulation(s) as sim:
+        q = torch.from_numpy(s.q).cuda()
+        sim.set_state(q)
+        dt = 0.9 * sim.compute_dt()
+        plain = sim.adjoint_step(q, lam, dt)
+        with_src = sim.adjoint_step(q, lam, dt, src=src)
+        in_place = sim.adjoint_step(q, lam, dt, src=lam)  # the source may be the input itself
+        assert torch.equal(with_src, plain + src)
+        assert torch.equal(in_place, plain + lam)

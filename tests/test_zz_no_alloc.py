@@ -44,10 +44,10 @@ def test_noalloc_adjoint_equals_the_allocating_one_on_two_calls(bn, torch_cuda):
             sim.set_state(q)
             dt = 0.9 * sim.compute_dt()
             gref = torch.zeros(s.nx, dtype=torch.float64, device="cuda")
-            ref = sim.adjoint_step(q, lam, dt, grad_bottom=gref)
+            ref = sim.adjoint_step(q, lam, dt, grad_bottom=gref, src=q)
             out = torch.full_like(q, float("nan"))
             gout = torch.full_like(gref, float("nan"))
-            sim.adjoint_step_noalloc(q, lam, dt, out, grad_bottom=gout)
+            sim.adjoint_step_noalloc(q, lam, dt, out, grad_bottom=gout, src=q)
             torch.cuda.synchronize()
         ref, out = ref.cpu().numpy(), out.cpu().numpy()
         assert np.all(np.isfinite(out))
@@ -57,7 +57,7 @@ def test_noalloc_adjoint_equals_the_allocating_one_on_two_calls(bn, torch_cuda):
 
 def test_noalloc_adjoint_rejects_a_grid_beyond_its_array(bn, torch_cuda):
     torch = torch_cuda
-    s = sc.dam_break_small(1024, 512)  # 77 planes of 524288 cells > 2^24 doubles
+    s = sc.dam_break_small(1024, 512)  # 38 planes of 524288 cells (19.9 M doubles) > 2^24
     with bn.Simulation(s) as sim:
         q = torch.from_numpy(np.ascontiguousarray(s.q)).cuda()
         out = torch.zeros_like(q)
