@@ -1,7 +1,11 @@
-// Attainable-peak probes for the roofline of the step kernel (measurement only, not part of the
-// method's ABI): FP64 FMA throughput on the vector ALUs and HBM bandwidth of a triad.
+// Probes beside the library (measurement only, not part of the method's ABI): attainable peaks for
+// the step kernel's roofline (FP64 FMA throughput on the vector ALUs, HBM bandwidth of a triad), and
+// the accuracy of the reciprocal the physics uses (bn::rcp: the hardware estimate refined by one
+// Newton step) against the correctly rounded quotient.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "bn2d_physics.h"
 
 namespace {
 
@@ -31,9 +35,45 @@ __global__ __launch_bounds__(256) void triad_kernel(double *a, const double *b, 
         a[i] = b[i] + s * c[i];
 }
 
+// distance in units of the last place between bn::rcp(x) and the correctly rounded 1/x, for n
+// log-uniformly spaced x in [2^lo, 2^hi]; the largest into *worst
+__global__ __launch_bounds__(256) void rcp_kernel(long long n, double lo, double hi, unsigned long long *worst)
+{
+    unsigned long long m = 0;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const double x = exp2(lo + (hi - lo) * ((double)k + 0.5) / (double)n);
+        const double r = bn::rcp(x), q = 1.0 / x;
+        const long long d = __double_as_longlong(r) - __double_as_longlong(q);
+        const unsigned long long u = (unsigned long long)(d < 0 ? -d : d);
+        m = u > m ? u : m;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(worst, m);
+}
+
 }  // namespace
 
 extern "C" {
+
+// Largest distance in ulps between the physics' reciprocal and 1/x over n log-uniform x in
+// [2^lo, 2^hi] (x > 0): 0 and *max_ulps, or a negative code.
+int bn_probe_rcp(long long n, double lo, double hi, unsigned long long *max_ulps)
+{
+    if (n <= 0 || !(hi > lo) || !max_ulps) return -1;
+    unsigned long long *w = nullptr;
+    if (hipMalloc(&w, sizeof(unsigned long long)) != hipSuccess) return -2;
+    hipError_t e = hipMemset(w, 0, sizeof(unsigned long long));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(rcp_kernel, dim3(1024), dim3(256), 0, 0, n, lo, hi, w);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(max_ulps, w, sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    (void)hipFree(w);
+    return e == hipSuccess ? 0 : -2;
+}
 
 // FP64 FMA rate: `blocks` x 256 threads, each `iters` x 16 x 8 dependent-free FMAs.  Returns 0 and
 // the FLOP/s (2 per FMA) of the best of `reps` launches, or a HIP error code.
