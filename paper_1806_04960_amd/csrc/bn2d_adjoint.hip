@@ -111,6 +111,7 @@ __device__ __forceinline__ void load_stencil(const AdjArgs &a, int i, int j, dou
 }
 
 struct ArrayStencil {
+    static constexpr bool kRingFlags = false;
     const double (*wq)[3][4];
     const int (*wf)[3];
     __device__ __forceinline__ double q(int dj, int di, int k) const { return wq[dj][di][k]; }

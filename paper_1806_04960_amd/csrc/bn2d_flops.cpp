@@ -71,6 +71,7 @@ Consts make_consts(int nx, int ny, double x0, double x1, double y0, double y1, d
 }
 
 struct ArrayStencil {
+    static constexpr bool kRingFlags = false;
     const real_t (*wq)[3][4];
     const int (*wf)[3];
     real_t q(int dj, int di, int k) const { return wq[dj][di][k]; }

@@ -37,6 +37,18 @@ struct Consts {
 // Cell flags: fluid, outside the grid on a side, and (F_TX, F_TY) outside across a transmissive
 // side in x or y.  Solid cells and cells outside across a reflective wall are mirrored.
 enum : int { F_FLUID = 1, F_OUTW = 2, F_OUTE = 4, F_OUTS = 8, F_OUTN = 16, F_TX = 32, F_TY = 64 };
+// Bits that stencils with S::kRingFlags add to the flags of their cells once per cell: a fluid cell
+// without liquid (alpha <= 10 alpha_gas, Sec. 3.4), so that the second-order test of a window is one
+// test of its flags, and for a cell that is not fluid whether its mirror image negates the x (F_MX)
+// and the y (F_MY) momentum of the centre (a solid cell, or one outside across a reflective side).
+enum : int { F_LOWA = 128, F_MX = 256, F_MY = 512 };
+
+BN_DEV int mirror_bits(int f)
+{
+    const bool outx = f & (F_OUTW | F_OUTE), outy = f & (F_OUTS | F_OUTN);
+    const bool inside = !outx && !outy;
+    return ((inside || (outx && !(f & F_TX))) ? F_MX : 0) | ((inside || (outy && !(f & F_TY))) ? F_MY : 0);
+}
 
 // Flags of cell (i, j) of an nx x ny grid with boundary types bc (W, E, S, N; 1 transmissive).
 BN_DEV int cell_flags(int i, int j, int nx, int ny, const int bc[4], bool fluid)
@@ -49,7 +61,21 @@ BN_DEV int cell_flags(int i, int j, int nx, int ny, const int bc[4], bool fluid)
     return f;
 }
 
-BN_DEV real_t sgn(real_t x) { return (real_t)((x > 0.0) - (x < 0.0)); }
+BN_DEV real_t sgn(real_t x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// A constant read once for the whole wavefront and held in scalar registers.  A per-lane choice
+// between two constants is then a register select: left to itself the compiler may turn it into a
+// per-lane vector load from the chosen field's address, whose memory latency every later wait for
+// vector memory then pays.
+#ifdef BN2D_HOST_COUNT
+BN_DEV real_t uniform(real_t x) { return x; }
+#else
+BN_DEV double uniform(double x)
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+#endif
 
 // 1/x: the hardware reciprocal (relative error about 2^-24) refined by one Newton step, whose
 // error is the square of that: within 16 ulps of the quotient (at most 11 measured over 4 M
@@ -283,19 +309,29 @@ BN_DEV void reconstruct(const Consts &K, const S &st, int j, real_t y0c, real_t 
     const real_t *Qc = wq[1][1];
     const real_t yc = K.ylo + (j + 0.5) * K.dy;
     const bool liquid = yc < y0c;
-    const real_t aE = liquid ? K.al : K.ag;
+    const real_t aE = liquid ? uniform(K.al) : uniform(K.ag);
     // (the exponential only where some lane holds a liquid-type cell: gas rows skip it)
     real_t rE0 = K.rho0;
     if (any_lane(liquid)) rE0 = liquid ? K.rho0 * exp(-K.a * (yc - y0c)) : K.rho0;
     const real_t e1c = aE * rE0;
     r.aE = aE;
 
-    bool so = Qc[3] > K.so_thr;
+    bool so;
+    if constexpr (S::kRingFlags) {
+        int any = 0;
 #pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
+        for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
-        for (int di = 0; di < 3; ++di)
-            if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > K.so_thr)) so = false;
+            for (int di = 0; di < 3; ++di) any |= wf[dj][di];
+        so = !(any & F_LOWA);
+    } else {
+        so = Qc[3] > K.so_thr;
+#pragma unroll
+        for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+            for (int di = 0; di < 3; ++di)
+                if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > K.so_thr)) so = false;
+    }
 
     if (!so) {
 #pragma unroll
@@ -315,18 +351,23 @@ BN_DEV void reconstruct(const Consts &K, const S &st, int j, real_t y0c, real_t 
     // solid/outside neighbours mirror the centre across each reflective wall), then per component
     // central gradients and the Barth-Jespersen limiter over the four edge midpoints, whose two
     // x (y) midpoints carry +-d so that their ratios are (max - c)/|d| and (c - min)/|d|.
+    // (the centre is a fluid cell: its fluctuation is fc)
     real_t phi[3][3][4];
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
         for (int di = 0; di < 3; ++di) {
+            if (dj == 1 && di == 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) phi[1][1][k] = fc[k];
+                continue;
+            }
             // (selects rather than branches: both forms are a few operations)
             const int f = wf[dj][di];
             const bool fluid = f & F_FLUID;
-            const bool outx = f & (F_OUTW | F_OUTE), outy = f & (F_OUTS | F_OUTN);
-            const bool inside = !outx && !outy;
-            const bool fx = (di != 1) && (inside || (outx && !(f & F_TX)));
-            const bool fy = (dj != 1) && (inside || (outy && !(f & F_TY)));
+            const int mb = S::kRingFlags ? f : mirror_bits(f);
+            const bool fx = (di != 1) && (mb & F_MX);
+            const bool fy = (dj != 1) && (mb & F_MY);
             phi[dj][di][0] = fluid ? wq[dj][di][0] - e1row[dj] : fc[0];
             phi[dj][di][1] = fluid ? wq[dj][di][1] : (fx ? -fc[1] : fc[1]);
             phi[dj][di][2] = fluid ? wq[dj][di][2] : (fy ? -fc[2] : fc[2]);

@@ -217,6 +217,7 @@ struct Chunks {
 
 // Stencil accessor over the LDS ring: rows s[0..2] (below, centre, above), lane offsets -1..1.
 struct LdsStencil {
+    static constexpr bool kRingFlags = true;
     const double (*sq)[4][64];
     const int (*sf)[64];
     int s[3];
@@ -267,6 +268,7 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     const bool out_lane = colin && lane >= 2 && lane < 62;
     const bool rec_lane = lane >= 1 && lane <= 62;
     const size_t plane = (size_t)nx * ny;
+    const int fcol = cell_flags(i, 0, nx, 1, member_ref(mab).K.bc, false);
     double y0c = 0.0;
     if (colin) {
         const Member &M = member_ref(mab);
@@ -288,23 +290,26 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     int nF = 0;
     long long colfix = 0;
 
-    // row prefetch
+    // row prefetch (through a global-memory pointer: a generic one makes flat loads, which count
+    // against the same wait counter as scalar and LDS loads, so that the next wait for a constant
+    // would also wait for the row)
+    typedef const __attribute__((address_space(1))) double *GlobalRow;
+    const GlobalRow Qg = (GlobalRow)Qp;
     double lq[4];
-    int lf;
+    int ls = 0;  // the row's mask byte, turned into cell flags only when the row is stored (a use
+                 // right after the load would wait for it, and for every store still in flight)
     // (the address is clamped into the grid and the value replaced outside it, so that the load
     // needs no branch)
     auto load_row = [&](int r) {
         const bool in = colin && r >= 0 && r < ny;
         const size_t cidx = (size_t)min(max(r, 0), ny - 1) * nx + min(max(i, 0), nx - 1);
-        bool fluid = in;
-        if (solid) fluid = fluid && solid[cidx] == 0;
+        if (solid) ls = solid[cidx];
         const double dflt[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double v = Qp[k * plane + cidx];
+            const double v = Qg[k * plane + cidx];
             lq[k] = in ? v : dflt[k];
         }
-        lf = cell_flags(i, r, nx, ny, member_ref(mab).K.bc, fluid);
     };
     load_row(j0 - 2);
 
@@ -330,7 +335,14 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         __syncthreads();  // the slot about to be overwritten is no longer read
 #pragma unroll
         for (int k = 0; k < 4; ++k) sq[s_hi][k][lane] = lq[k];
-        sf[s_hi][lane] = lf;
+        // (a cell's flags are its column's, fixed for the march, and its row's, the same in every
+        // lane; and its low-alpha or mirror bits)
+        {
+            const Consts &K = member_ref(mab).K;
+            const bool fluid = colin && r >= 0 && r < ny && ls == 0;
+            const int f = fcol | cell_flags(0, r, 1, ny, K.bc, fluid);
+            sf[s_hi][lane] = f | (fluid ? (lq[3] > K.so_thr ? 0 : F_LOWA) : mirror_bits(f));
+        }
         if (!final_row) load_row(r + 1);
         __syncthreads();
         if (r < j0) continue;
