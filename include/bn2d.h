@@ -148,6 +148,23 @@ const char *bn_strerror(int code);
 int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
                     double *grad_bottom_dev, const double *src_dev);
 
+/* The free-surface column integrals of the context's current state (Sec. 3.5: per column the sum
+ * over its fluid cells of (alpha - alpha_g) / (alpha_l - alpha_g)), in the library's 64-bit fixed
+ * point (exact, independent of the order of summation): nx words into the caller-owned device
+ * buffer sums_dev, the values a step from that state uses.  The step that produced the state (or
+ * bn_set_state) computed them, so this is a copy of nx words.  For bn_adjoint_step_sums.
+ * Asynchronous on the context's stream.  Errors: BN_EINVAL (null pointer), BN_EHIP. */
+int bn_get_column_sums(bn_ctx *ctx, int64_t *sums_dev);
+
+/* bn_adjoint_step with the free-surface column integrals of q_dev given instead of computed from
+ * q_dev again: sums_dev, nx words, is what bn_get_column_sums returned for a context of the same
+ * grid, model and bottoms whose state was q_dev (e.g. the context that recomputed q_dev on another
+ * stream).  Bitwise the same lambda as bn_adjoint_step, one kernel fewer on the context's stream.
+ * Other values in sums_dev give a wrong result, not an error.  Other arguments, ownership, scratch,
+ * stream and errors as bn_adjoint_step (BN_EINVAL also for a null sums_dev). */
+int bn_adjoint_step_sums(bn_ctx *ctx, const double *q_dev, const int64_t *sums_dev, const double *lam_next_dev,
+                         double dt, double *lam_dev, double *grad_bottom_dev, const double *src_dev);
+
 /* bn_adjoint_step without any allocation, for callers that cannot allocate device memory (code
  * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments, result
  * and errors as bn_adjoint_step (bitwise the same lambda: the same kernels), but the scratch is a

@@ -17,7 +17,8 @@ BN_OK, BN_EINVAL, BN_EHIP, BN_ENONPHYS, BN_EUNSUPPORTED, BN_ENOMEM, BN_EINTERNAL
 
 SYMBOLS = ("bn_create", "bn_set_state", "bn_get_state", "bn_compute_dt", "bn_step", "bn_run",
            "bn_get_time", "bn_get_y0", "bn_status", "bn_set_bottom", "bn_set_launch", "bn_get_launch",
-           "bn_destroy", "bn_strerror", "bn_adjoint_step", "bn_adjoint_step_noalloc", "bn_batch_create",
+           "bn_destroy", "bn_strerror", "bn_adjoint_step", "bn_adjoint_step_noalloc", "bn_get_column_sums",
+           "bn_adjoint_step_sums", "bn_batch_create",
            "bn_batch_set_state", "bn_batch_get_state", "bn_batch_run", "bn_batch_get_time", "bn_batch_get_y0",
            "bn_batch_status", "bn_batch_set_bottom", "bn_batch_set_launch", "bn_batch_get_launch",
            "bn_batch_destroy")
@@ -68,6 +69,8 @@ def lib():
         L.bn_set_bottom.argtypes = [vp, dp]
         L.bn_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp]
         L.bn_adjoint_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.bn_get_column_sums.argtypes = [vp, vp]
+        L.bn_adjoint_step_sums.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]
         L.bn_strerror.argtypes = [ctypes.c_int]
         L.bn_strerror.restype = ctypes.c_char_p
         i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
@@ -178,12 +181,32 @@ class Simulation:
     def run(self, n_steps: int):
         check(lib().bn_run(self._ctx, int(n_steps)), "bn_run")
 
-    def adjoint_step(self, q, lam_next, dt: float, out=None, grad_bottom=None, src=None):
+    def adjoint_step(self, q, lam_next, dt: float, out=None, grad_bottom=None, src=None, sums=None):
         """lambda^n = (dQ^{n+1}/dQ^n)^T lambda^{n+1} (+ src) for the step of length dt from state q
         (``bn_adjoint_step``).  q, lam_next, src: contiguous float64 CUDA tensors [4, ny, nx].  With
         ``grad_bottom`` (a float64 CUDA tensor [nx]) also (dQ^{n+1}/dy_L)^T lambda^{n+1} of the
-        columns' bottom heights."""
-        return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out, grad_bottom, src)
+        columns' bottom heights.  With ``sums`` (``column_sums()`` of a context of this grid whose
+        state was q) the free surface of q is taken from it (``bn_adjoint_step_sums``): the same
+        result, one kernel fewer."""
+        import torch
+        if sums is None:
+            return self._adjoint(lib().bn_adjoint_step, "bn_adjoint_step", q, lam_next, dt, out, grad_bottom, src)
+        if not (sums.is_cuda and sums.dtype == torch.int64 and sums.is_contiguous() and tuple(sums.shape) == (self.nx,)):
+            raise ValueError(f"sums must be a contiguous int64 CUDA tensor of shape ({self.nx},)")
+        fn = lib().bn_adjoint_step_sums
+        return self._adjoint(lambda ctx, qp, *rest: fn(ctx, qp, ctypes.c_void_p(sums.data_ptr()), *rest),
+                             "bn_adjoint_step_sums", q, lam_next, dt, out, grad_bottom, src)
+
+    def column_sums(self, out=None):
+        """The free-surface column integrals of the current state (``bn_get_column_sums``: int64
+        fixed point, [nx]) for ``adjoint_step(..., sums=...)``."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nx, dtype=torch.int64, device="cuda")
+        elif not (out.is_cuda and out.dtype == torch.int64 and out.is_contiguous() and tuple(out.shape) == (self.nx,)):
+            raise ValueError(f"out must be a contiguous int64 CUDA tensor of shape ({self.nx},)")
+        check(lib().bn_get_column_sums(self._ctx, ctypes.c_void_p(out.data_ptr())), "bn_get_column_sums")
+        return out
 
     def adjoint_step_noalloc(self, q, lam_next, dt: float, out, grad_bottom=None, src=None):
         """The same adjoint through ``bn_adjoint_step_noalloc``: the library's fixed scratch array,
@@ -426,6 +449,9 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
     C = len(ck)
     sizes = [min(seg, N - c * seg) for c in range(C)]
     bufs = [[torch.empty_like(ck[0]) for _ in range(max(seg - 1, 0))] for _ in range(2)]
+    # the free-surface column sums of every state of a segment, from the twin that recomputes it
+    # (its step computed them), so that the reverse sweep does not compute them again
+    sums = [[torch.empty(sim.nx, dtype=torch.int64, device=w.device) for _ in range(seg)] for _ in range(2)]
     ev_rec = [torch.cuda.Event() for _ in range(C)]
     ev_rev = [torch.cuda.Event() for _ in range(C)]
     # (the checkpoints and weights were written on the context's stream)
@@ -433,9 +459,11 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
 
     def recompute(c):
         twin.set_state(ck[c])
+        twin.column_sums(out=sums[c % 2][0])
         for k in range(1, sizes[c]):
             twin.step(dt)
             twin.get_state(out=bufs[c % 2][k - 1])
+            twin.column_sums(out=sums[c % 2][k])
         ev_rec[c].record(sb)
 
     recompute(C - 1)
@@ -450,7 +478,7 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
             q = ck[c] if k == 0 else bufs[c % 2][k - 1]
             # lam = dJ/dQ^{n0+k+1} in; out dJ/dQ^{n0+k}, with that step's own term w added (none for q0)
             lam = sim.adjoint_step(q, lam, dt, grad_bottom=None if gsteps is None else gsteps[n0 + k],
-                                   src=w if n0 + k > 0 else None)
+                                   src=w if n0 + k > 0 else None, sums=sums[c % 2][k])
         ev_rev[c].record(sa)
     sa.wait_stream(sb)
     if gbot is not None and N > 0:
@@ -498,6 +526,7 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
     if store_all:
         states = [q0.detach().clone()]
         sim.set_state(states[0])
+        sums = [sim.column_sums()]
         J = torch.zeros((), dtype=torch.float64, device=q0.device)
         for k in range(N):
             sim.step(dt)
@@ -507,11 +536,12 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
                     J += (w * q).sum()
                 if k + 1 < N:
                     states.append(q)
+                    sums.append(sim.column_sums())
         lam = w.clone() if N > 0 else torch.zeros_like(w)  # dJ/dQ^N
         gsteps = torch.empty((N, sim.nx), dtype=torch.float64, device=q0.device) if bottom else None
         for n in range(N - 1, -1, -1):
             lam = sim.adjoint_step(states[n], lam, dt, grad_bottom=None if gsteps is None else gsteps[n],
-                                   src=w if n > 0 else None)
+                                   src=w if n > 0 else None, sums=sums[n])
         if bottom and N > 0:
             gbot += gsteps.sum(dim=0)
         sim.set_state(states[0])

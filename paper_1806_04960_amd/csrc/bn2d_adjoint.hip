@@ -96,6 +96,11 @@ __device__ __forceinline__ double y0_of(const AdjArgs &a, int i)
 __device__ __forceinline__ void load_stencil(const AdjArgs &a, int i, int j, double (&wq)[3][3][4], int (&wf)[3][3])
 {
     const size_t plane = (size_t)a.K.nx * a.K.ny;
+    // (through a global-memory pointer: with a generic one the choice between the state and the
+    // default below becomes one flat load from either address, which every later wait for an LDS or
+    // scalar load then also waits for)
+    typedef const __attribute__((address_space(1))) double *GlobalQ;
+    const GlobalQ qg = (GlobalQ)a.q;
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
@@ -105,7 +110,10 @@ __device__ __forceinline__ void load_stencil(const AdjArgs &a, int i, int j, dou
             const size_t c = in ? (size_t)jj * a.K.nx + ii : 0;
             const double dflt[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) wq[dj][di][k] = in ? a.q[k * plane + c] : dflt[k];
+            for (int k = 0; k < 4; ++k) {
+                const double v = qg[k * plane + c];
+                wq[dj][di][k] = in ? v : dflt[k];
+            }
             wf[dj][di] = flags_at(a, ii, jj);
         }
 }

@@ -697,12 +697,12 @@ int bn_get_launch(bn_ctx *c, int32_t *rows_per_block, int32_t *wavefronts)
     return bn_batch_get_launch(c->b, rows_per_block, wavefronts);
 }
 
-int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
-                    double *grad_bottom_dev, const double *src_dev)
+}  // extern "C"
+
+namespace {
+// The adjoint's scratch, allocated on a context's first adjoint step and kept until bn_destroy.
+int adjoint_scratch(Grid &g)
 {
-    if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
-    bn_batch *b = c->b;
-    Grid &g = b->g[0];
     const int nx = g.grid.nx, ny = g.grid.ny;
     if (!g.adj) {
         hipError_t e = hipMalloc(&g.adj, sizeof(double) * bn_adjoint_scratch(nx, ny));
@@ -715,12 +715,52 @@ int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, 
             return BN_ENOMEM;
         }
     }
+    return BN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int bn_adjoint_step(bn_ctx *c, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
+                    double *grad_bottom_dev, const double *src_dev)
+{
+    if (!c || !q_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt)) return BN_EINVAL;
+    bn_batch *b = c->b;
+    Grid &g = b->g[0];
+    int rc = adjoint_scratch(g);
+    if (rc) return rc;
     // the free-surface integral of the given state, exactly as a step from it would use it
     long long *S = g.adjS;
-    const int rc = adjoint_colsum(b, g, q_dev, S);
+    rc = adjoint_colsum(b, g, q_dev, S);
     if (rc) return rc;
-    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S, colsum_blocks(ny),
-                              g.dev.fix_inv, dt, g.adj, grad_bottom_dev, src_dev, b->stream));
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot, S,
+                              colsum_blocks(g.grid.ny), g.dev.fix_inv, dt, g.adj, grad_bottom_dev, src_dev, b->stream));
+    return BN_OK;
+}
+
+int bn_get_column_sums(bn_ctx *c, int64_t *sums_dev)
+{
+    if (!c || !sums_dev) return BN_EINVAL;
+    bn_batch *b = c->b;
+    Grid &g = b->g[0];
+    HIP_TRY(hipMemcpyAsync(sums_dev, g.S + (size_t)b->m3 * g.grid.nx, sizeof(long long) * g.grid.nx,
+                           hipMemcpyDeviceToDevice, b->stream));
+    return BN_OK;
+}
+
+int bn_adjoint_step_sums(bn_ctx *c, const double *q_dev, const int64_t *sums_dev, const double *lam_next_dev,
+                         double dt, double *lam_dev, double *grad_bottom_dev, const double *src_dev)
+{
+    if (!c || !q_dev || !sums_dev || !lam_next_dev || !lam_dev || !(dt > 0.0) || !std::isfinite(dt))
+        return BN_EINVAL;
+    bn_batch *b = c->b;
+    Grid &g = b->g[0];
+    const int rc = adjoint_scratch(g);
+    if (rc) return rc;
+    // the given column sums are the whole integral: one partial per column
+    HIP_TRY(bn_adjoint_launch(g.dev.K, q_dev, lam_next_dev, lam_dev, g.solid, g.jb, g.dbot,
+                              reinterpret_cast<const long long *>(sums_dev), 1, g.dev.fix_inv, dt, g.adj,
+                              grad_bottom_dev, src_dev, b->stream));
     return BN_OK;
 }
 

@@ -405,3 +405,40 @@ def test_source_term_is_added_to_the_adjoint(bn, torch_cuda):
         in_place = sim.adjoint_step(q, lam, dt, src=lam)  # the source may be the input itself
         assert torch.equal(with_src, plain + src)
         assert torch.equal(in_place, plain + lam)
+
+
+def test_adjoint_step_with_given_column_sums(bn, torch_cuda):
+    """bn_get_column_sums / bn_adjoint_step_sums: the column sums a step leaves for the state it made
+    are bitwise those bn_set_state computes for that state, and the adjoint step given them is bitwise
+    bn_adjoint_step (lambda and the bottom-height gradient, with a source term), on a wall-impact grid
+    whose wall top lies off the grid."""
+    torch = torch_cuda
+    s = sc.generic_state(sc.wall_impact(0, 40, 20), seed=5)
+    iw = s.meta["wall_column"]
+    s.bottom[iw] += 0.3 * s.dy
+    rng = np.random.default_rng(6)
+    lam = torch.from_numpy(rng.normal(size=s.q.shape)).cuda()
+    src = torch.from_numpy(rng.normal(size=s.q.shape)).cuda()
+    with bn.Simulation(s) as sim:
+        q0 = torch.from_numpy(s.q).cuda()
+        sim.set_state(q0)
+        dt = 0.9 * sim.compute_dt()
+        sums0 = sim.column_sums()
+        sim.step(dt)
+        q1 = sim.get_state()
+        sums_step = sim.column_sums()
+        sim.set_state(q1)
+        sums_set = sim.column_sums()
+        assert torch.equal(sums_step, sums_set)
+        assert not torch.equal(sums0, sums_step)
+        for q, sums in ((q0, sums0), (q1, sums_step)):
+            gb_a = torch.zeros(s.nx, dtype=torch.float64, device="cuda")
+            gb_b = torch.ones(s.nx, dtype=torch.float64, device="cuda")
+            plain = sim.adjoint_step(q, lam, dt, grad_bottom=gb_a, src=src)
+            given = sim.adjoint_step(q, lam, dt, grad_bottom=gb_b, src=src, sums=sums)
+            assert torch.equal(plain, given) and torch.equal(gb_a, gb_b)
+            assert float(gb_a.abs().max()) > 0.0
+        with pytest.raises(ValueError):
+            sim.adjoint_step(q1, lam, dt, sums=sums_step[:-1])
+        with pytest.raises(ValueError):
+            sim.adjoint_step(q1, lam, dt, sums=sums_step.double())

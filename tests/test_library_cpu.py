@@ -27,6 +27,18 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_declares_every_signature():
+    """Every entry point has its ctypes argument types (a call without them fails on a double
+    argument), with as many arguments as the header's prototype."""
+    L = bn2d.lib()
+    text = open(os.path.join(ROOT, "include", "bn2d.h")).read()
+    for name in bn2d.SYMBOLS:
+        m = re.search(r"\b" + name + r"\s*\(([^)]*)\)", text)
+        n_args = len([a for a in m.group(1).split(",") if a.strip() and a.strip() != "void"])
+        assert getattr(L, name).argtypes is not None, name
+        assert len(getattr(L, name).argtypes) == n_args, name
+
+
 def test_strerror_names_every_code():
     L = bn2d.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -99):
