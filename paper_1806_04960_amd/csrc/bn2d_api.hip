@@ -20,8 +20,8 @@ __global__ void reduce_kernel(const double *Q, const uint8_t *solid, long long *
                               unsigned long long *lam_slot, int *flag, Consts K, int H);
 __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, int *flag, Consts K);
 __global__ void colsum_kernel(const double *Q, const uint8_t *solid, long long *S, double fix_scale, Consts K, int H);
-__global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
-                                     long long nrows, double *Ts_in, double *Ts_acc, const bn::StripInfo *strips,
+__global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int *unowned, int R0, int max_slots,
+                                     float *cost, long long nrows, double *Ts_in, double *Ts_acc, const bn::StripInfo *strips,
                                      int nstrips);
 __global__ void zero_kernel(long long *p, int n);
 __global__ void y0_kernel(const long long *S, const int *jb, const double *dbot, const double *Q, double fix_inv,
@@ -180,7 +180,7 @@ struct bn_batch {
     bn::Member *members = nullptr;       // [count] on the device
     bn::Control *ctl = nullptr;          // [6] on the device: combination 3 par + m3
     unsigned long long *desc = nullptr;  // [2][max_slots]
-    int *nranges = nullptr;              // [2]
+    int *nranges = nullptr;              // [3]: range counts [2], unowned ranges
     float *cost = nullptr;               // [2][nrows]
     double *Ts = nullptr;                // [3][nstrips]
     bn::StripInfo *strips = nullptr;     // [nstrips]
@@ -255,6 +255,7 @@ int write_tables(bn_batch *b)
             C.Ts_clear = b->Ts + ((mm + 2) % 3) * ns;
             C.strips = b->strips;
             C.flag = b->flag;
+            C.unowned = b->nranges + 2;
             C.nstrips = b->nstrips;
             C.nmembers = (int)b->g.size();
             C.R0 = b->R0;
@@ -272,7 +273,8 @@ int init_schedule(bn_batch *b)
     const long long n = std::max<long long>(std::max<long long>(b->nrows, b->max_slots), b->nstrips);
     const size_t ns = b->nstrips;
     hipLaunchKernelGGL(bn::init_schedule_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream,
-                       b->desc + (size_t)b->par * b->max_slots, b->nranges + b->par, b->R0, b->max_slots,
+                       b->desc + (size_t)b->par * b->max_slots, b->nranges + b->par, b->nranges + 2, b->R0,
+                       b->max_slots,
                        b->cost + (size_t)b->par * b->nrows, b->nrows, b->Ts + (size_t)b->m3 * ns,
                        b->Ts + (size_t)((b->m3 + 1) % 3) * ns, b->strips, b->nstrips);
     HIP_TRY(hipGetLastError());
@@ -443,14 +445,14 @@ int bn_batch_create(int32_t count, const bn_grid *grids, const bn_params *params
     }
     ALLOC(b->members, sizeof(bn::Member) * count);
     ALLOC(b->ctl, sizeof(bn::Control) * 6);
-    ALLOC(b->nranges, sizeof(int) * 2);
+    ALLOC(b->nranges, sizeof(int) * 3);  // two range counts and the unowned count
     ALLOC(b->cost, sizeof(float) * 2 * (size_t)b->nrows);
     ALLOC(b->Ts, sizeof(double) * 3 * (size_t)b->nstrips);
     ALLOC(b->strips, sizeof(bn::StripInfo) * (size_t)b->nstrips);
     ALLOC(b->flag, sizeof(int));
 #undef ALLOC
     e = hipMemcpy(b->strips, strips.data(), sizeof(bn::StripInfo) * strips.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->nranges, 0, sizeof(int) * 2);
+    if (e == hipSuccess) e = hipMemset(b->nranges, 0, sizeof(int) * 3);
     if (e == hipSuccess) e = hipMemset(b->flag, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(b->Ts, 0, sizeof(double) * 3 * (size_t)b->nstrips);
     if (e != hipSuccess) {

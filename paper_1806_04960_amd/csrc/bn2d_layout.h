@@ -48,6 +48,7 @@ struct Control {
     double *Ts_clear;               // third buffer, zeroed for the next step
     const StripInfo *strips;        // every global strip
     int *flag;                      // batch-wide scheduler error (4)
+    int *unowned;                   // ranges published unowned and not taken yet (0 between steps)
     int nstrips;                    // global strips
     int nmembers;
     int R0;                         // initial descriptors: one per wavefront, one head per strip

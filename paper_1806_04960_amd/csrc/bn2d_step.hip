@@ -472,12 +472,44 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
 // A split costs the thief a halo (two extra reconstructed rows and a row of loads), so only ranges
 // with at least this many unclaimed rows are split.
 constexpr int kMinSplit = 3;
-constexpr int kScanBatch = 40;  // descriptors per lane loaded at once by a thief
+constexpr int kScanBatch = 40;  // descriptors per lane loaded at once by a thief's full scan
+constexpr int kSample = 2;      // descriptors per lane of a thief's first look
+
+// Search key of descriptor word d in slot s for thief attempt `attempt`, 0 if it offers nothing:
+// score << 40 | hash << 32 | (2^31 - 1 - slot), larger is better.  Unowned ranges first, then by size
+// class (floor log2 of the unclaimed rows); within a class a hash of (slot, thief) spreads the
+// thieves over the victims.
+__device__ __forceinline__ long long steal_key(unsigned long long d, int s, int attempt)
+{
+    const int rem = d_end(d) - d_cur(d);
+    long long score = 0;
+    if (!(d & kOwned) && rem >= 1) score = 64 + (31 - __clz(rem));
+    else if ((d & kOwned) && rem >= kMinSplit) score = 31 - __clz(rem);
+    if (score == 0) return 0;
+    const unsigned h = ((unsigned)s * 2654435761u) ^ ((unsigned)blockIdx.x * 40503u + attempt);
+    return (score << 40) | ((long long)(h & 0xFFu) << 32) | (long long)(0x7FFFFFFF - s);
+}
+
+__device__ __forceinline__ long long wave_max(long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
 
 // Find work: a range nobody owns (taken whole) or a large range being marched with at least
 // kMinSplit unclaimed rows (upper half taken).  Returns false when there is none.  On success the
 // caller has claimed rows [*j0, *E) of strip *strip and owns descriptor *slot (-1: the rows up to
 // *E are all it gets, when the descriptor list is full).
+// A thief first looks at 64 kSample descriptors spread over the list (a phase of its own per
+// attempt) and takes the best of them; it scans every descriptor only when that look finds nothing
+// while some range is still unowned.  (Near the end of a step most searches find nothing: a full
+// scan by every finishing wavefront loads the whole list each time and delays the last ones.  An
+// unowned range is always found: its publisher counted it before publishing it, and its own
+// search, after its own range, scans everything while the count is positive.)
 __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E, int *slot)
 {
     const int lane = threadIdx.x;
@@ -485,37 +517,43 @@ __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E,
     for (int attempt = 0; attempt < 4096; ++attempt) {
         int n = __hip_atomic_load(a.nranges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         n = n < a.max_slots ? n : a.max_slots;
-        // key = score << 40 | hash << 32 | (2^31 - 1 - slot): larger is better
+        if (n <= 0) return false;
         long long best = 0;
-        // (all of a batch's loads are in flight together: one batch covers a launch's initial
-        // descriptors and its first splits)
-        for (int base = 0; base < n; base += 64 * kScanBatch) {
-            unsigned long long wd[kScanBatch];
+        {
+            const int stride = max(1, n / (64 * kSample));
+            const int phase = (int)(((unsigned)blockIdx.x * 2654435761u + (unsigned)attempt * 40503u) % (unsigned)n);
+            unsigned long long wd[kSample];
+            int ws[kSample];
 #pragma unroll
-            for (int u = 0; u < kScanBatch; ++u) {
-                const int s = base + u * 64 + lane;
-                wd[u] = s < n ? load_word(a.desc + s) : 0ull;
+            for (int u = 0; u < kSample; ++u) {
+                ws[u] = (int)(((long long)phase + (long long)(u * 64 + lane) * stride) % n);
+                wd[u] = load_word(a.desc + ws[u]);
             }
 #pragma unroll
-            for (int u = 0; u < kScanBatch; ++u) {
-                const int s = base + u * 64 + lane;
-                const int rem = d_end(wd[u]) - d_cur(wd[u]);
-                // unowned ranges first, then by size class (floor log2 of the unclaimed rows);
-                // within a class a hash of (slot, thief) spreads the thieves over the victims
-                long long score = 0;
-                if (!(wd[u] & kOwned) && rem >= 1) score = 64 + (31 - __clz(rem));
-                else if ((wd[u] & kOwned) && rem >= kMinSplit) score = 31 - __clz(rem);
-                if (score > 0 && s < n) {
-                    const unsigned h = ((unsigned)s * 2654435761u) ^ ((unsigned)blockIdx.x * 40503u + attempt);
-                    const long long key = (score << 40) | ((long long)(h & 0xFFu) << 32) | (long long)(0x7FFFFFFF - s);
+            for (int u = 0; u < kSample; ++u) {
+                const long long key = steal_key(wd[u], ws[u], attempt);
+                best = key > best ? key : best;
+            }
+            best = wave_max(best);
+        }
+        if (best == 0 && __hip_atomic_load(a.unowned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+            // (all of a batch's loads are in flight together: one batch covers a launch's initial
+            // descriptors and its first splits)
+            for (int base = 0; base < n; base += 64 * kScanBatch) {
+                unsigned long long wd[kScanBatch];
+#pragma unroll
+                for (int u = 0; u < kScanBatch; ++u) {
+                    const int s = base + u * 64 + lane;
+                    wd[u] = s < n ? load_word(a.desc + s) : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < kScanBatch; ++u) {
+                    const int s = base + u * 64 + lane;
+                    const long long key = s < n ? steal_key(wd[u], s, attempt) : 0;
                     best = key > best ? key : best;
                 }
             }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const long long o = __shfl_xor(best, off, 64);
-            best = o > best ? o : best;
+            best = wave_max(best);
         }
         if (best == 0) return false;
         const int s = 0x7FFFFFFF - (int)(best & 0xFFFFFFFFll);
@@ -527,6 +565,7 @@ __device__ bool steal(unsigned long long ca, int B, int *strip, int *j0, int *E,
             if (!(old & kOwned) && end - cur >= 1) {
                 if (atomicCAS(p, old, (old | kOwned) + (unsigned long long)B) == old) {
                     ok = 1; st = d_strip(old); r0 = cur; r1 = min(cur + B, end); sl = s;
+                    atomicSub(a.unowned, 1);
                 }
             } else if ((old & kOwned) && end - cur >= kMinSplit) {
                 const int mid = cur + (end - cur) / 2;
@@ -627,7 +666,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
                 j0 = lo;
                 E = min(lo + a.B, hi);
             }
-            // strips the share spans whole are left unowned (a strip cheaper than a share)
+            // strips the share spans whole are left unowned (a strip cheaper than a share), counted
+            // first: thieves scan every descriptor while the count is positive
+            const int n_unowned = min(g_next, C.nstrips) - (g_w + 1);
+            if (lane == 0 && n_unowned > 0) atomicAdd(C.unowned, n_unowned);
             for (int s = g_w + 1 + lane; s < g_next && s < C.nstrips; s += 64)
                 atomicExch(C.desc + P + s, d_make(false, s, C.strips[s].ny, 0));
             // the head of the strip the share ends in is this wavefront's too: published owned and
@@ -745,9 +787,9 @@ __global__ void dt_kernel(const unsigned long long *lam_slot, double *dt_out, in
 
 // Schedule state of the next step after bn_set_state or a change of the launch shape: empty
 // descriptor list, uniform recorded costs (1 per row), cleared strip totals to accumulate into.
-__global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int R0, int max_slots, float *cost,
-                                     long long nrows, double *Ts_in, double *Ts_acc, const StripInfo *strips,
-                                     int nstrips)
+__global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int *unowned, int R0, int max_slots,
+                                     float *cost, long long nrows, double *Ts_in, double *Ts_acc,
+                                     const StripInfo *strips, int nstrips)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < max_slots) desc[s] = 0ull;
@@ -756,7 +798,10 @@ __global__ void init_schedule_kernel(unsigned long long *desc, int *nranges, int
         Ts_in[s] = (double)strips[s].ny;
         Ts_acc[s] = 0.0;
     }
-    if (s == 0) *nranges = R0;
+    if (s == 0) {
+        *nranges = R0;
+        *unowned = 0;
+    }
 }
 
 __global__ void zero_kernel(long long *p, int n)
