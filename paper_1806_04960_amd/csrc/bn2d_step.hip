@@ -379,14 +379,23 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
             const int fR = shfl_from_right(fc_mid);
             const bool rf = (lane <= 61) && (fR & F_FLUID);
             double qm[4], qp[4], Dm[4], Dp[4];
+            // (every reconstructing lane fluid, the usual case: no mirror states, a uniform branch)
+            if (all_lanes(!rec_lane || fl)) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                qm[k] = fl ? rc.qE[k] : qWr[k];
-                qp[k] = rf ? qWr[k] : rc.qE[k];
+                for (int k = 0; k < 4; ++k) {
+                    qm[k] = rc.qE[k];
+                    qp[k] = qWr[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    qm[k] = fl ? rc.qE[k] : qWr[k];
+                    qp[k] = rf ? qWr[k] : rc.qE[k];
+                }
+                // wall: mirror state with negated normal momentum, or a copy on a transmissive side
+                if (!fl && !(fc_mid & F_TX)) qm[1] = -qm[1];
+                if (!rf && !(fR & F_TX)) qp[1] = -qp[1];
             }
-            // wall: mirror state with negated normal momentum, or a copy on a transmissive side
-            if (!fl && !(fc_mid & F_TX)) qm[1] = -qm[1];
-            if (!rf && !(fR & F_TX)) qp[1] = -qp[1];
             edge_x(K, qm, qp, Dm, Dp);
             double DpW[4];
 #pragma unroll
