@@ -414,31 +414,55 @@ def step_function():
     return StepFn
 
 
-def _trajectory_forward(sim, q0, dt: float, N: int, w, seg: int, with_loss: bool):
-    """N steps of length dt from q0: the loss sum_n <w, Q^n> (if asked) and the checkpoints."""
+def _segment_buffers(sim, like, seg: int):
+    """Two sets of buffers for the states of a segment after its checkpoint (seg - 1 states) and the
+    free-surface column sums of all its states (seg), one set per segment in flight."""
     import torch
 
+    bufs = [[torch.empty_like(like) for _ in range(max(seg - 1, 0))] for _ in range(2)]
+    sums = [[torch.empty(sim.nx, dtype=torch.int64, device=like.device) for _ in range(seg)] for _ in range(2)]
+    return bufs, sums
+
+
+def _trajectory_forward(sim, q0, dt: float, N: int, w, seg: int, with_loss: bool, last=None):
+    """N steps of length dt from q0: the loss sum_n <w, Q^n> (if asked) and the checkpoints.  With
+    ``last`` = (states, sums), one buffer set of ``_segment_buffers``, the states of the last segment
+    and the column sums of its states are kept there as they are computed, so that the reverse sweep
+    need not recompute that segment before it can start."""
+    import torch
+
+    C = 1 + (N - 1) // seg if N > 0 else 1
+    n0 = (C - 1) * seg  # the last segment's first state
     ck = [q0.detach().clone()]
     sim.set_state(ck[0])
+    if last is not None and n0 == 0:
+        sim.column_sums(out=last[1][0])
     J = torch.zeros((), dtype=torch.float64, device=q0.device)
     for k in range(N):
         sim.step(dt)
-        keep = (k + 1) % seg == 0 and k + 1 < N
+        m = k + 1  # the state just computed
+        keep = m % seg == 0 and m < N
         if with_loss or keep:
             q = sim.get_state()
             if with_loss:
                 J += (w * q).sum()
             if keep:
                 ck.append(q)
+        if last is not None and n0 <= m < N:
+            if m > n0:
+                sim.get_state(out=last[0][m - n0 - 1])
+            sim.column_sums(out=last[1][m - n0])
     return J, ck
 
 
-def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
+def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None, buffers=None, last_ready=False):
     """dJ/dq0 from the checkpoints: each segment, last first, recomputed and reversed (and, into
     ``gbot`` if given, the sum over the steps of the bottom heights' adjoints).  The segments are
     recomputed on the context's twin, on a stream of its own, one segment ahead of the reverse sweep
     on the context's stream: segment c - 1 is recomputed while segment c is reversed (two sets of
-    state buffers; events order a set's reuse after the sweep that reads it)."""
+    state buffers; events order a set's reuse after the sweep that reads it).  ``buffers``: the sets
+    of ``_segment_buffers``; with ``last_ready`` the last segment's set was filled by the forward run
+    (``_trajectory_forward(..., last=...)``) and is not recomputed."""
     import torch
 
     twin = sim.twin()
@@ -448,10 +472,9 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
     gsteps = None if gbot is None else torch.empty((N, gbot.numel()), dtype=gbot.dtype, device=gbot.device)
     C = len(ck)
     sizes = [min(seg, N - c * seg) for c in range(C)]
-    bufs = [[torch.empty_like(ck[0]) for _ in range(max(seg - 1, 0))] for _ in range(2)]
-    # the free-surface column sums of every state of a segment, from the twin that recomputes it
+    # the free-surface column sums of every state of a segment come from the twin that recomputes it
     # (its step computed them), so that the reverse sweep does not compute them again
-    sums = [[torch.empty(sim.nx, dtype=torch.int64, device=w.device) for _ in range(seg)] for _ in range(2)]
+    bufs, sums = buffers if buffers is not None else _segment_buffers(sim, ck[0], seg)
     ev_rec = [torch.cuda.Event() for _ in range(C)]
     ev_rev = [torch.cuda.Event() for _ in range(C)]
     # (the checkpoints and weights were written on the context's stream)
@@ -466,7 +489,10 @@ def _trajectory_reverse(sim, ck, dt: float, N: int, w, seg: int, gbot=None):
             twin.column_sums(out=sums[c % 2][k])
         ev_rec[c].record(sb)
 
-    recompute(C - 1)
+    if last_ready:
+        ev_rec[C - 1].record(sa)
+    else:
+        recompute(C - 1)
     for c in range(C - 1, -1, -1):
         if c >= 1:
             if c + 1 < C:
@@ -546,8 +572,11 @@ def trajectory_gradient(sim, q0, dt: float, n_steps: int, weights, segment: int 
             gbot += gsteps.sum(dim=0)
         sim.set_state(states[0])
         return result(J, lam)
-    J, ck = _trajectory_forward(sim, q0, dt, N, w, seg, with_loss)
-    lam = _trajectory_reverse(sim, ck, dt, N, w, seg, gbot)
+    buffers = _segment_buffers(sim, q0, seg)
+    C = 1 + (N - 1) // seg if N > 0 else 1
+    J, ck = _trajectory_forward(sim, q0, dt, N, w, seg, with_loss,
+                                last=(buffers[0][(C - 1) % 2], buffers[1][(C - 1) % 2]))
+    lam = _trajectory_reverse(sim, ck, dt, N, w, seg, gbot, buffers=buffers, last_ready=True)
     return result(J, lam)
 
 

@@ -227,6 +227,23 @@ def test_checkpointed_trajectory_gradient(bn, torch_cuda):
         assert abs(ad - fd2) <= TOL * abs(fd2)
 
 
+@pytest.mark.parametrize("N,seg", [(1, 1), (4, 1), (4, 3), (6, 3), (7, 20)])
+def test_checkpointed_gradient_at_segment_edges(bn, torch_cuda, N, seg):
+    """The checkpointed gradient (the last segment kept by the forward run, the others recomputed) is
+    bitwise the gradient over every stored state, for segments of one step, trajectories that end on
+    a checkpoint and one shorter than a segment."""
+    torch = torch_cuda
+    s = sc.smooth_state(sc.wall_impact(0, nx=32, ny=16))
+    w = torch.from_numpy(np.random.default_rng(8).standard_normal(s.q.shape) * s.fluid()).cuda()
+    q0 = torch.from_numpy(s.q).cuda()
+    with bn.Simulation(s) as sim:
+        sim.set_state(q0)
+        dt = sim.compute_dt()
+        g_ck, gb_ck = bn.trajectory_gradient(sim, q0, dt, N, w, segment=seg, bottom=True)
+        g_all, gb_all = bn.trajectory_gradient(sim, q0, dt, N, w, store_all=True, bottom=True)
+    assert torch.equal(g_ck, g_all) and torch.equal(gb_ck, gb_all)
+
+
 def test_trajectory_gradient_of_no_steps_is_zero(bn, torch_cuda):
     s = sc.wall_impact(0, nx=16, ny=8)
     q0 = torch_cuda.from_numpy(s.q).cuda()
