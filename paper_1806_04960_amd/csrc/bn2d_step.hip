@@ -105,14 +105,37 @@ __device__ __forceinline__ double shfl_from_right(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// v from a lane src that is the same in every lane: scalar reads of its halves, no LDS round trip
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int lane_value(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// A DPP move of both halves of v (lanes the pattern does not reach, or rows outside row_mask, get 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_or_zero(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), kCtrl, kRowMask, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive prefix sum over the wavefront by DPP (a fixed order of additions, the same in every
+// wavefront): within each row of 16 lanes by shifts of 1, 2, 4 and 8, then lane 15 of rows 0 and 2
+// added to rows 1 and 3, then lane 31 to rows 2 and 3.
 __device__ __forceinline__ double wave_incl_scan(double v)
 {
-    const int lane = threadIdx.x;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
+    v += dpp_or_zero<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_or_zero<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_or_zero<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_or_zero<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_or_zero<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp_or_zero<0x143, 0xC>(v);  // row_bcast:31
     return v;
 }
 
@@ -159,7 +182,7 @@ struct Chunks {
         }
         incl = wave_incl_scan(sum);
         excl = incl - sum;
-        total = __shfl(incl, 63, 64);
+        total = lane_value(incl, 63);
     }
 
     __device__ void find(double t, int &idx, double &off) const
@@ -188,12 +211,12 @@ struct Chunks {
                 }
                 acc = next;
             }
-            found = __shfl(found, l, 64);
-            rem = __shfl(rem, l, 64);
+            found = lane_value(found, l);
+            rem = lane_value(rem, l);
         } else {
             // the wavefront walks lane l's entries 64 at a time
-            const int lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
-            double acc = __shfl(excl, l, 64);
+            const int lb = lane_value(b, l), le = lane_value(e, l);
+            double acc = lane_value(excl, l);
             found = le - 1;
             rem = 0.0;
             for (int c = lb; c < le; c += 64) {
@@ -204,10 +227,10 @@ struct Chunks {
                 if (hit) {
                     const int u = __ffsll((long long)hit) - 1;
                     found = c + u;
-                    rem = t - (acc + __shfl(si - x, u, 64));
+                    rem = t - (acc + lane_value(si - x, u));
                     break;
                 }
-                acc += __shfl(si, 63, 64);
+                acc += lane_value(si, 63);
             }
         }
         idx = found;
