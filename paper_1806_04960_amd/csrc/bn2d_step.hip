@@ -170,15 +170,25 @@ struct Chunks {
         }
 #pragma unroll
         for (int u = 0; u < kHeld; ++u) sum += vv[u];
-        for (int c = b + kHeld; c < e; c += 16) {
-            double w[16];
+        if (sizeof(T) == sizeof(float) && m > kHeld && m <= 64) {
+            // up to 64 single-precision entries a lane: the rest in one more round of loads, summed
+            // in the same order
+            T w[64 - kHeld];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const double x = (double)v[min(c + u, n - 1)];
-                w[u] = c + u < e ? x : 0.0;
+            for (int u = 0; u < 64 - kHeld; ++u) w[u] = v[min(b + kHeld + u, n - 1)];
+#pragma unroll
+            for (int u = 0; u < 64 - kHeld; ++u) sum += b + kHeld + u < e ? (double)w[u] : 0.0;
+        } else {
+            for (int c = b + kHeld; c < e; c += 16) {
+                double w[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const double x = (double)v[min(c + u, n - 1)];
+                    w[u] = c + u < e ? x : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) sum += w[u];
             }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) sum += w[u];
         }
         incl = wave_incl_scan(sum);
         excl = incl - sum;
