@@ -64,15 +64,11 @@ constexpr int kColRows = 32;
 constexpr int kRecPlanes = 21;
 enum : int { P_QW = 0, P_QE = 4, P_QS = 8, P_QN = 12, P_E1S = 16, P_E1N = 17, P_AE = 18, P_YS = 19, P_YN = 20 };
 
+typedef const __attribute__((address_space(1))) double *GlobalD;
 __device__ __forceinline__ bool fluid_at(const AdjArgs &a, int i, int j)
 {
     if (i < 0 || i >= a.K.nx || j < 0 || j >= a.K.ny) return false;
     return !a.solid || a.solid[(size_t)j * a.K.nx + i] == 0;
-}
-
-__device__ __forceinline__ int flags_at(const AdjArgs &a, int i, int j)
-{
-    return cell_flags(i, j, a.K.nx, a.K.ny, a.K.bc, fluid_at(a, i, j));
 }
 
 // 1 - (alpha - alpha_g)/(alpha_l - alpha_g) of column i's first fluid cell (0 for a full cell)
@@ -91,30 +87,45 @@ __device__ __forceinline__ double y0_of(const AdjArgs &a, int i)
     return v;
 }
 
+// the mask byte read for every cell when a grid has no solid cells
+__device__ const uint8_t kNoSolid[1] = {0};
+
 // The 3 x 3 stencil of cell (i, j): states (outside the grid: the benign (1, 0, 0, 1), never used)
-// and flags.
+// and flags.  Every load is issued before any is used (clamped addresses, values replaced outside
+// the grid): a mask byte tested as soon as it is loaded would wait for it, and for every load before
+// it.  (Through global-memory pointers: with a generic one the choice between the state and the
+// default becomes one flat load from either address, which every later wait for an LDS or scalar
+// load then also waits for.)
 __device__ __forceinline__ void load_stencil(const AdjArgs &a, int i, int j, double (&wq)[3][3][4], int (&wf)[3][3])
 {
-    const size_t plane = (size_t)a.K.nx * a.K.ny;
-    // (through a global-memory pointer: with a generic one the choice between the state and the
-    // default below becomes one flat load from either address, which every later wait for an LDS or
-    // scalar load then also waits for)
-    typedef const __attribute__((address_space(1))) double *GlobalQ;
-    const GlobalQ qg = (GlobalQ)a.q;
+    const int nx = a.K.nx, ny = a.K.ny;
+    const size_t plane = (size_t)nx * ny;
+    typedef const __attribute__((address_space(1))) uint8_t *GlobalMask;
+    const GlobalD qg = (GlobalD)a.q;
+    const GlobalMask sg = (GlobalMask)(a.solid ? a.solid : kNoSolid);
+    int mb[3][3];
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
         for (int di = 0; di < 3; ++di) {
             const int ii = i + di - 1, jj = j + dj - 1;
-            const bool in = ii >= 0 && ii < a.K.nx && jj >= 0 && jj < a.K.ny;
-            const size_t c = in ? (size_t)jj * a.K.nx + ii : 0;
+            const bool in = ii >= 0 && ii < nx && jj >= 0 && jj < ny;
+            const size_t c = (size_t)min(max(jj, 0), ny - 1) * nx + min(max(ii, 0), nx - 1);
+            mb[dj][di] = (int)sg[a.solid ? c : 0];
             const double dflt[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const double v = qg[k * plane + c];
                 wq[dj][di][k] = in ? v : dflt[k];
             }
-            wf[dj][di] = flags_at(a, ii, jj);
+        }
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+        for (int di = 0; di < 3; ++di) {
+            const int ii = i + di - 1, jj = j + dj - 1;
+            const bool in = ii >= 0 && ii < nx && jj >= 0 && jj < ny;
+            wf[dj][di] = cell_flags(ii, jj, nx, ny, a.K.bc, in && mb[dj][di] == 0);
         }
 }
 
@@ -138,17 +149,17 @@ constexpr int kTX = 64, kTY = 4, kHX = kTX + 2, kHY = kTY + 2, kHalo = kHX * kHY
 // x-edge between local columns e-1 and e (e = 0..64) of tile row ty; qmb/qpb: the adjoints of the
 // left cell's east state and of the right cell's west state (a missing side mirrors the fluid one,
 // so its share is folded into the fluid side's)
-__device__ __forceinline__ void fused_xedge(const AdjArgs &a, const double (*sr)[kHalo], int i0, int j0, int e, int ty,
-                                            double qmb[4], double qpb[4], bool &flL, bool &flR)
+__device__ __forceinline__ void fused_xedge(const AdjArgs &a, const double (*sr)[kHalo], const int *sf, int i0, int j0,
+                                            int e, int ty, double qmb[4], double qpb[4], bool &flL, bool &flR)
 {
     const int iL = i0 + e - 1, iR = i0 + e, j = j0 + ty;
-    flL = fluid_at(a, iL, j);
-    flR = fluid_at(a, iR, j);
+    const int hL = (ty + 1) * kHX + e, hR = hL + 1;  // halo-record indices of the two cells
+    const int fL = sf[hL], fR = sf[hR];
+    flL = fL & F_FLUID;
+    flR = fR & F_FLUID;
 #pragma unroll
     for (int k = 0; k < 4; ++k) qmb[k] = qpb[k] = 0.0;
     if (!flL && !flR) return;
-    const int fL = flags_at(a, iL, j), fR = flags_at(a, iR, j);
-    const int hL = (ty + 1) * kHX + e, hR = hL + 1;  // halo-record indices of the two cells
     const size_t n = (size_t)a.K.nx * a.K.ny;
     double qm[4], qp[4];
 #pragma unroll
@@ -161,11 +172,13 @@ __device__ __forceinline__ void fused_xedge(const AdjArgs &a, const double (*sr)
     qm[1] *= sL;
     qp[1] *= sR;
     const size_t cL = flL ? (size_t)j * a.K.nx + iL : 0, cR = flR ? (size_t)j * a.K.nx + iR : 0;
+    const GlobalD lg = (GlobalD)a.lam1;
     double Dmb[4], Dpb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Dmb[k] = flL ? -a.dtdx * a.lam1[k * n + cL] : 0.0;
-        Dpb[k] = flR ? -a.dtdx * a.lam1[k * n + cR] : 0.0;
+        const double lL = lg[k * n + cL], lR = lg[k * n + cR];
+        Dmb[k] = flL ? -a.dtdx * lL : 0.0;
+        Dpb[k] = flR ? -a.dtdx * lR : 0.0;
     }
     double bm[4] = {0, 0, 0, 0}, bp[4] = {0, 0, 0, 0};
     edge_x_rev(a.K, qm, qp, Dmb, Dpb, bm, bp);
@@ -179,17 +192,17 @@ __device__ __forceinline__ void fused_xedge(const AdjArgs &a, const double (*sr)
 }
 
 // y-edge between local rows e-1 and e (e = 0..4) of tile column tx
-__device__ __forceinline__ void fused_yedge(const AdjArgs &a, const double (*sr)[kHalo], int i0, int j0, int tx, int e,
-                                            double qmb[5], double qpb[5], bool &flB, bool &flT)
+__device__ __forceinline__ void fused_yedge(const AdjArgs &a, const double (*sr)[kHalo], const int *sf, int i0, int j0,
+                                            int tx, int e, double qmb[5], double qpb[5], bool &flB, bool &flT)
 {
     const int i = i0 + tx, jB = j0 + e - 1, jT = j0 + e;
-    flB = fluid_at(a, i, jB);
-    flT = fluid_at(a, i, jT);
+    const int hB = e * kHX + tx + 1, hT = hB + kHX;
+    const int fB = sf[hB], fT = sf[hT];
+    flB = fB & F_FLUID;
+    flT = fT & F_FLUID;
 #pragma unroll
     for (int k = 0; k < 5; ++k) qmb[k] = qpb[k] = 0.0;
     if (!flB && !flT) return;
-    const int fB = flags_at(a, i, jB), fT = flags_at(a, i, jT);
-    const int hB = e * kHX + tx + 1, hT = hB + kHX;
     const size_t n = (size_t)a.K.nx * a.K.ny;
     double qNB[4], qST[4];
 #pragma unroll
@@ -212,11 +225,13 @@ __device__ __forceinline__ void fused_yedge(const AdjArgs &a, const double (*sr)
     const double e1m = flB ? e1NB : e1ST, aEm = flB ? aEB : aET, ym = flB ? yN : yS;
     const double e1p = flT ? e1ST : e1NB, aEp = flT ? aET : aEB, yp = flT ? yS : yN;
     const size_t cB = flB ? (size_t)jB * a.K.nx + i : 0, cT = flT ? (size_t)jT * a.K.nx + i : 0;
+    const GlobalD lg = (GlobalD)a.lam1;
     double Dmb[4], Dpb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Dmb[k] = flB ? -a.dtdy * a.lam1[k * n + cB] : 0.0;
-        Dpb[k] = flT ? -a.dtdy * a.lam1[k * n + cT] : 0.0;
+        const double lB = lg[k * n + cB], lT = lg[k * n + cT];
+        Dmb[k] = flB ? -a.dtdy * lB : 0.0;
+        Dpb[k] = flT ? -a.dtdy * lT : 0.0;
     }
     double bm[4] = {0, 0, 0, 0}, bp[4] = {0, 0, 0, 0}, e1mb = 0.0, e1pb = 0.0;
     edge_y_rev(a.K, qm, e1m, aEm, ym, qp, e1p, aEp, yp, Dmb, Dpb, bm, e1mb, bp, e1pb);
@@ -235,6 +250,7 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
 {
     __shared__ double sr[kRecPlanes][kHalo];  // records, then (planes 0..17, first 256 entries) face adjoints
     __shared__ double sy0[kHX];               // free-surface heights of the tile's columns and halo
+    __shared__ int sf[kHalo];                 // flags of the tile's cells and halo
     const int t = threadIdx.x;
     const int i0 = (int)blockIdx.x * kTX, j0 = (int)blockIdx.y * kTY;
     if (t < kHX && i0 + t - 1 >= 0 && i0 + t - 1 < a.K.nx) sy0[t] = y0_of(a, i0 + t - 1);
@@ -243,10 +259,11 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     // (a) records of the tile and its halo
     for (int h = t; h < kHalo; h += 256) {
         const int i = i0 + h % kHX - 1, j = j0 + h / kHX - 1;
-        if (!fluid_at(a, i, j)) continue;
         double wq[3][3][4];
         int wf[3][3];
         load_stencil(a, i, j, wq, wf);
+        sf[h] = wf[1][1];
+        if (!(wf[1][1] & F_FLUID)) continue;
         Rec r;
         ArrayStencil st{wq, wf};
         reconstruct(a.K, st, j, sy0[h % kHX], a.dt, r);
@@ -273,10 +290,10 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     for (int u = 0; u < 2; ++u) {
         const int ex = t + 256 * u;
         xl[u] = xr[u] = false;
-        if (ex < nX) fused_xedge(a, sr, i0, j0, ex % (kTX + 1), ex / (kTX + 1), xm[u], xp[u], xl[u], xr[u]);
+        if (ex < nX) fused_xedge(a, sr, sf, i0, j0, ex % (kTX + 1), ex / (kTX + 1), xm[u], xp[u], xl[u], xr[u]);
         const int ey = t + 256 * u;
         yb[u] = yt[u] = false;
-        if (ey < nY) fused_yedge(a, sr, i0, j0, ey % kTX, ey / kTX, ym[u], yp[u], yb[u], yt[u]);
+        if (ey < nY) fused_yedge(a, sr, sf, i0, j0, ey % kTX, ey / kTX, ym[u], yp[u], yb[u], yt[u]);
     }
     __syncthreads();  // every record read: the face adjoints go over them
     // face adjoint of tile cell c = ty * 64 + tx in sr[plane][c]; a cell outside the tile or not
@@ -317,13 +334,13 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     if (i >= a.K.nx || j >= a.K.ny) return;
     const size_t n = (size_t)a.K.nx * a.K.ny;
     const size_t c = (size_t)j * a.K.nx + i;
-    if (!fluid_at(a, i, j)) {
-        a.y0b[c] = 0.0;
-        return;
-    }
     double wq[3][3][4];
     int wf[3][3];
     load_stencil(a, i, j, wq, wf);
+    if (!(wf[1][1] & F_FLUID)) {
+        a.y0b[c] = 0.0;
+        return;
+    }
     bool so = wq[1][1][3] > a.K.so_thr;
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
