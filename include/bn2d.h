@@ -142,7 +142,7 @@ const char *bn_strerror(int code);
  * column).  src_dev: NULL, or a caller-owned device buffer in the state layout added to the result
  * (lam_dev = (d Q^{n+1} / d Q^n)^T lam_next_dev + src_dev): the per-step term dJ/dQ^n of a loss summed
  * over a trajectory, so that a reverse sweep needs no separate addition; it may be lam_next_dev
- * itself but must not overlap lam_dev.  The library allocates its scratch (about 38 doubles per cell) on the first call and keeps
+ * itself but must not overlap lam_dev.  The library allocates its scratch (about 6.5 doubles per cell) on the first call and keeps
  * it until bn_destroy.  Asynchronous on the context's stream.  Errors: BN_EINVAL (null pointer, dt <= 0
  * or not finite), BN_ENOMEM, BN_EHIP.  A non-physical q_dev gives non-finite values. */
 int bn_adjoint_step(bn_ctx *ctx, const double *q_dev, const double *lam_next_dev, double dt, double *lam_dev,
@@ -170,8 +170,9 @@ int bn_adjoint_step_sums(bn_ctx *ctx, const double *q_dev, const int64_t *sums_d
  * and errors as bn_adjoint_step (bitwise the same lambda: the same kernels), but the scratch is a
  * fixed library array of 2^24 doubles (128 MiB) per GPU, reserved when the library's device code is
  * loaded and held until the process ends, instead of memory allocated on the first call.  The grid
- * must fit: 38 nx ny + nx (ceil(ny / 32) + ceil(ny / 16)) <= 2^24 (about 440 000 cells, e.g. 512 x 256
- * or 768 x 512), else BN_EINVAL before any work is enqueued.  The first call on a device resolves the
+ * must fit: 4 nx ny + 560 ceil(nx / 64) ceil(ny / 4) + nx (ceil(ny / 4) + ceil(ny / 16) + 1) <= 2^24
+ * (about 2.5 million cells, e.g. 2048 x 1024; not 2048 x 2048), else BN_EINVAL before any work is
+ * enqueued.  The first call on a device resolves the
  * array's address on that device (the current device must be the context's).  Every call on a GPU
  * uses that GPU's one array: calls that overlap in time on one GPU (other streams, other contexts,
  * other threads) race and give wrong results; calls ordered on one stream, or synchronised, do not.

@@ -8,27 +8,29 @@
 //   D-+(e)      = edge_x / edge_y of the two edge states of e (a wall or solid side mirrors the
 //                 fluid side's state)
 //   Q^{n+1}_c   = Q^n_c - dt/dx (D+_W + D-_E + fdiff) - dt/dy (D+_S + D-_N + gdiff) - dt vol
-// is reversed in three launches through library-owned planes:
+// is reversed in three launches through library-owned scratch:
 //   1. adj_fused_kernel   per tile of 64 x 4 cells: recompute Rec of the tile and its one-cell halo
 //                         into LDS, reverse every x- and y-edge touching the tile (recompute D-+ and
 //                         reverse it with the adjoints of the two cells' updates; the adjoints of
 //                         the tile cells' edge states go back into LDS: each edge state feeds exactly
-//                         one edge, no accumulation), then reverse each tile cell's reconstruction:
-//                         adjoints of its 3 x 3 stencil (36 planes; a first-order cell reaches only
-//                         itself and writes only that entry and a 0 in the second-order flag plane)
-//                         and of y0_i (1 plane)
-//   2. adj_col_kernel     sum the y0 adjoints of each column, in blocks of kColRows rows (the
-//                         gather adds the blocks' partial sums in order: deterministic)
+//                         one edge, no accumulation), then reverse each tile cell's reconstruction
+//                         (adjoints of its 3 x 3 stencil, of a first-order cell only its own entry,
+//                         and of y0_i) and sum the stencil adjoints per target cell in LDS: the
+//                         tile's cells' sums (4 planes), those falling on the halo (140 cells per
+//                         tile) and the tile's share of each column's y0 adjoint
+//   2. adj_col_kernel     add the tiles' shares of each column's y0 adjoint in row order; and (if
+//                         asked) the adjoint of each column's bottom height: its y0 adjoint times
+//                         dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g) (0 for a column
+//                         without fluid cells)
 //   3. adj_gather_kernel  lambda^n_c = lambda^{n+1}_c + the stencil adjoints of the (up to 9)
-//                         fluid cells whose stencil holds c (of a first-order neighbour only
-//                         c's own entry) + the detector's dy/(alpha_l - alpha_g) times its column's
-//                         y0 adjoint (alpha only; (dy - d)/(alpha_l - alpha_g) in the first fluid
-//                         cell of a column whose bottom lies d off the grid); solid cells pass
-//                         lambda through (their state is copied and never read); and (if asked) the
-//                         adjoint of each column's bottom height: its y0 adjoint times dy0/dy_L =
-//                         (alpha_l - alpha_first) / (alpha_l - alpha_g), written by the column's
-//                         first fluid cell; an optional source (e.g. dJ/dQ^n of a trajectory loss) is
-//                         added to lambda^n last
+//                         fluid cells whose stencil holds c (the own tile's sum, then those the
+//                         neighbouring tiles left on their halos) + the detector's
+//                         dy/(alpha_l - alpha_g) times its column's y0 adjoint (alpha only;
+//                         (dy - d)/(alpha_l - alpha_g) in the first fluid cell of a column whose
+//                         bottom lies d off the grid); solid cells pass lambda through (their state
+//                         is copied and never read); an optional source (e.g. dJ/dQ^n of a
+//                         trajectory loss) is added to lambda^n last
+// Every sum is taken in a fixed order: the result is deterministic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,15 +50,14 @@ struct AdjArgs {
     int nSp;
     double fix_inv;
     double dt, dtdx, dtdy;
-    double *wb;             // 36 planes (a first-order cell writes only its own entry, (1, 1))
-    double *y0b;            // 1 plane (0 for solid cells)
-    double *sob;            // 1 plane: 1 where the fluid cell's reconstruction is second order
-    double *colb;           // [ceil(ny / kColRows)][nx] partial column sums
+    double *own;            // 4 planes: per cell, the stencil adjoints of its own tile's cells
+    double *ring;           // [tiles][4][kRing]: those falling on each tile's halo
+    double *colb;           // [ceil(ny / kTY)][nx]: each tile's share of the columns' y0 adjoints
+    double *colt;           // [nx]: the columns' y0 adjoints
     double *gbot;           // [nx] adjoint of the bottom heights, or null
     const double *src;      // 4 planes added to lambda^n, or null
 };
 
-constexpr int kColRows = 32;
 
 // record planes of the fused pass's LDS: qW 0-3, qE 4-7, qS 8-11, qN 12-15, e1S 16, e1N 17, aE 18,
 // yS 19, yN 20 (the heights of the S/N states: the edge's for a second-order cell, the centre's for a
@@ -142,9 +143,20 @@ struct ArrayStencil {
 // of the tile's cells and of a one-cell halo around it (66 x 6 cells) into LDS; (b) every x- and y-edge
 // touching a tile cell (65 x 4 and 64 x 5) is reversed from those records and the lambdas of its two
 // cells, the adjoints of the tile cells' edge states going back into LDS (over the records, after a
-// barrier); (c) each tile cell reverses its reconstruction.  The edge-state records and their
-// adjoints never reach HBM.
+// barrier); (c) each tile cell reverses its reconstruction; (d) the stencil adjoints are summed per
+// target cell in LDS.  The edge-state records and their adjoints never reach HBM, nor do the
+// per-stencil-entry adjoints.
 constexpr int kTX = 64, kTY = 4, kHX = kTX + 2, kHY = kTY + 2, kHalo = kHX * kHY;  // 396 records
+// the halo's 140 cells in ring order: the row below (66), the row above (66), the column left of the
+// tile's rows (4), the column right of them (4)
+constexpr int kRing = 2 * kHX + 2 * kTY;
+__device__ __forceinline__ int ring_cell(int r)
+{
+    if (r < kHX) return r;
+    if (r < 2 * kHX) return (kHY - 1) * kHX + (r - kHX);
+    if (r < 2 * kHX + kTY) return (r - 2 * kHX + 1) * kHX;
+    return (r - 2 * kHX - kTY + 1) * kHX + kHX - 1;
+}
 
 // x-edge between local columns e-1 and e (e = 0..64) of tile row ty; qmb/qpb: the adjoints of the
 // left cell's east state and of the right cell's west state (a missing side mirrors the fluid one,
@@ -329,39 +341,12 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     }
     __syncthreads();
 
-    // (c) the tile cell's reconstruction reversed
-    const int i = i0 + (t % kTX), j = j0 + t / kTX;
-    if (i >= a.K.nx || j >= a.K.ny) return;
+    // (c) the tile cell's reconstruction reversed (a cell outside the grid or not fluid adds nothing)
+    const int tx = t % kTX, ty = t / kTX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool in = i < a.K.nx && j < a.K.ny;
     const size_t n = (size_t)a.K.nx * a.K.ny;
-    const size_t c = (size_t)j * a.K.nx + i;
-    double wq[3][3][4];
-    int wf[3][3];
-    load_stencil(a, i, j, wq, wf);
-    if (!(wf[1][1] & F_FLUID)) {
-        a.y0b[c] = 0.0;
-        return;
-    }
-    bool so = wq[1][1][3] > a.K.so_thr;
-#pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-        for (int di = 0; di < 3; ++di)
-            if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > a.K.so_thr)) so = false;
-    RecBar rb;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        rb.qW[k] = sr[P_QW + k][t];
-        rb.qE[k] = sr[P_QE + k][t];
-        rb.qS[k] = sr[P_QS + k][t];
-        rb.qN[k] = sr[P_QN + k][t];
-        const double l = a.lam1[k * n + c];
-        rb.fdiff[k] = -a.dtdx * l;
-        rb.gdiff[k] = -a.dtdy * l;
-    }
-    rb.e1S = sr[P_E1S][t];
-    rb.e1N = sr[P_E1N][t];
-    rb.vol2 = -a.dt * a.lam1[2 * n + c];
-    rb.vol3 = -a.dt * a.lam1[3 * n + c];
+    const size_t c = in ? (size_t)j * a.K.nx + i : 0;
     double wqb[3][3][4];
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
@@ -369,35 +354,99 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
         for (int di = 0; di < 3; ++di)
 #pragma unroll
             for (int k = 0; k < 4; ++k) wqb[dj][di][k] = 0.0;
-    const double ybar = reconstruct_rev(a.K, wq, wf, j, sy0[(t % kTX) + 1], a.dt, rb, wqb);
-    if (so) {
+    bool act = false, so = false;
+    double ybar = 0.0;
+    if (in) {
+        double wq[3][3][4];
+        int wf[3][3];
+        load_stencil(a, i, j, wq, wf);
+        if (wf[1][1] & F_FLUID) {
+            act = true;
+            so = wq[1][1][3] > a.K.so_thr;
 #pragma unroll
-        for (int dj = 0; dj < 3; ++dj)
+            for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
-            for (int di = 0; di < 3; ++di)
+                for (int di = 0; di < 3; ++di)
+                    if ((wf[dj][di] & F_FLUID) && !(wq[dj][di][3] > a.K.so_thr)) so = false;
+            RecBar rb;
+            const GlobalD lg = (GlobalD)a.lam1;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) a.wb[((dj * 3 + di) * 4 + k) * n + c] = wqb[dj][di][k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a.wb[((1 * 3 + 1) * 4 + k) * n + c] = wqb[1][1][k];
+            for (int k = 0; k < 4; ++k) {
+                rb.qW[k] = sr[P_QW + k][t];
+                rb.qE[k] = sr[P_QE + k][t];
+                rb.qS[k] = sr[P_QS + k][t];
+                rb.qN[k] = sr[P_QN + k][t];
+                const double l = lg[k * n + c];
+                rb.fdiff[k] = -a.dtdx * l;
+                rb.gdiff[k] = -a.dtdy * l;
+            }
+            rb.e1S = sr[P_E1S][t];
+            rb.e1N = sr[P_E1N][t];
+            rb.vol2 = -a.dt * lg[2 * n + c];
+            rb.vol3 = -a.dt * lg[3 * n + c];
+            ybar = reconstruct_rev(a.K, wq, wf, j, sy0[tx + 1], a.dt, rb, wqb);
+        }
     }
-    a.sob[c] = so ? 1.0 : 0.0;
-    a.y0b[c] = ybar;
+    __syncthreads();  // every record read: the sums go over them
+
+    // (d) the stencil adjoints summed per target cell in LDS (planes 0-3 over the tile and its halo),
+    // one stencil entry after another: within one entry the targets of different cells differ, so
+    // every sum is taken in the fixed order of the entries (deterministic).  A first-order cell
+    // reaches only itself.  The y0 adjoints of the tile's cells go to plane 4.
+    for (int h = t; h < kHalo; h += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sr[k][h] = 0.0;
+    }
+    sr[4][t] = ybar;
+    __syncthreads();
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+        for (int di = 0; di < 3; ++di) {
+            if (act && (so || (dj == 1 && di == 1))) {
+                const int h = (ty + dj) * kHX + tx + di;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sr[k][h] += wqb[dj][di][k];
+            }
+            __syncthreads();
+        }
+    if (in) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.own[k * n + c] = sr[k][(ty + 1) * kHX + tx + 1];
+    }
+    // the sums that fall on the halo, for the neighbouring tiles' cells
+    const size_t tile = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (t < kRing) {
+        const int h = ring_cell(t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.ring[(tile * 4 + k) * kRing + t] = sr[k][h];
+    }
+    // the tile's share of each column's y0 adjoint (its rows in order; rows off the grid hold 0)
+    if (t < kTX && i0 + t < a.K.nx)
+        a.colb[(size_t)blockIdx.y * a.K.nx + i0 + t] =
+            ((sr[4][t] + sr[4][kTX + t]) + sr[4][2 * kTX + t]) + sr[4][3 * kTX + t];
 }
 
-// partial sum of rows [kColRows y, kColRows (y+1)) of column i (grid: columns / 64 x row blocks)
+// The y0 adjoint of column i: the tiles' shares added in row order; and the adjoint of the column's
+// bottom height, its y0 adjoint times dy0/dy_L (0 for a column without fluid cells).
 __global__ __launch_bounds__(64) void adj_col_kernel(AdjArgs a)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= a.K.nx) return;
-    const int j0 = (int)blockIdx.y * kColRows, j1 = min(a.K.ny, j0 + kColRows);
-    double v[kColRows];
+    const int nty = (a.K.ny + kTY - 1) / kTY;
+    const GlobalD cb = (GlobalD)a.colb;
+    double col = 0.0;
+    int by = 0;
+    for (; by + 8 <= nty; by += 8) {
+        double v[8];
 #pragma unroll
-    for (int u = 0; u < kColRows; ++u) v[u] = j0 + u < j1 ? a.y0b[(size_t)(j0 + u) * a.K.nx + i] : 0.0;
-    double s = 0.0;
+        for (int u = 0; u < 8; ++u) v[u] = cb[(size_t)(by + u) * a.K.nx + i];
 #pragma unroll
-    for (int u = 0; u < kColRows; ++u) s += v[u];
-    a.colb[(size_t)blockIdx.y * a.K.nx + i] = s;
+        for (int u = 0; u < 8; ++u) col += v[u];
+    }
+    for (; by < nty; ++by) col += cb[(size_t)by * a.K.nx + i];
+    a.colt[i] = col;
+    if (a.gbot) a.gbot[i] = a.jb[i] < a.K.ny ? col * first_gap(a, i) : 0.0;
 }
 
 __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
@@ -415,28 +464,32 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
         for (int k = 0; k < 4; ++k) add[k] = a.src[k * n + c];
     }
     if (fluid_at(a, i, j)) {
-        // stencil entry (dj, di) of the cell (i - di + 1, j - dj + 1) is this cell
+        // the sums of the cell's own tile, then those the neighbouring tiles left on their halos
+        // (left, right, below and its corners, above and its corners)
 #pragma unroll
-        for (int dj = 0; dj < 3; ++dj)
+        for (int k = 0; k < 4; ++k) out[k] += a.own[k * n + c];
+        const int ntx = (a.K.nx + kTX - 1) / kTX, nty = (a.K.ny + kTY - 1) / kTY;
+        const int bx = i / kTX, tx = i % kTX, by = j / kTY, ty = j % kTY;
+        const bool lf = tx == 0 && bx > 0, rt = tx == kTX - 1 && bx + 1 < ntx;
+        auto take = [&](int tbx, int tby, int r) {
+            const size_t tile = (size_t)tby * ntx + tbx;
 #pragma unroll
-            for (int di = 0; di < 3; ++di) {
-                const int ii = i - di + 1, jj = j - dj + 1;
-                if (!fluid_at(a, ii, jj)) continue;
-                const size_t m = (size_t)jj * a.K.nx + ii;
-                // a first-order cell stored only its own entry
-                if (!(dj == 1 && di == 1) && !(a.sob[m] != 0.0)) continue;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) out[k] += a.wb[((dj * 3 + di) * 4 + k) * n + m];
-            }
-        double col = 0.0;
-        for (int y = 0; y * kColRows < a.K.ny; ++y) col += a.colb[(size_t)y * a.K.nx + i];
+            for (int k = 0; k < 4; ++k) out[k] += a.ring[(tile * 4 + k) * kRing + r];
+        };
+        if (lf) take(bx - 1, by, 2 * kHX + kTY + ty);
+        if (rt) take(bx + 1, by, 2 * kHX + ty);
+        if (ty == 0 && by > 0) {
+            take(bx, by - 1, kHX + tx + 1);
+            if (lf) take(bx - 1, by - 1, 2 * kHX - 1);
+            if (rt) take(bx + 1, by - 1, kHX);
+        }
+        if (ty == kTY - 1 && by + 1 < nty) {
+            take(bx, by + 1, tx + 1);
+            if (lf) take(bx - 1, by + 1, kHX - 1);
+            if (rt) take(bx + 1, by + 1, 0);
+        }
         const double dy_eff = (a.dbot && j == a.jb[i]) ? a.K.dy - a.dbot[i] : a.K.dy;
-        out[3] += dy_eff / (a.K.al - a.K.ag) * col;
-        // the column's bottom height reaches the step through its free surface only:
-        // dy0/dy_L = 1 - a of the first fluid cell (written by that cell's thread)
-        if (a.gbot && j == a.jb[i]) a.gbot[i] = col * first_gap(a, i);
-    } else if (a.gbot && j == a.K.ny - 1 && a.jb[i] == a.K.ny) {
-        a.gbot[i] = 0.0;  // a column without fluid cells
+        out[3] += dy_eff / (a.K.al - a.K.ag) * a.colt[i];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.lam[k * n + c] = out[k] + add[k];
@@ -445,13 +498,10 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
 }  // namespace bn
 
 // Launch the passes on `stream`.  Scratch: bn_adjoint_scratch(nx, ny) doubles.
-namespace bn {
-constexpr int kAdjPlanes = 36 + 2;
-}
-
 size_t bn_adjoint_scratch(int nx, int ny)
 {
-    return (size_t)bn::kAdjPlanes * nx * ny + (size_t)nx * ((ny + bn::kColRows - 1) / bn::kColRows);
+    const size_t ntx = (nx + bn::kTX - 1) / bn::kTX, nty = (ny + bn::kTY - 1) / bn::kTY;
+    return 4 * (size_t)nx * ny + ntx * nty * 4 * bn::kRing + (size_t)nx * (nty + 1);
 }
 
 hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double *lam1, double *lam,
@@ -476,15 +526,14 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.dtdx = dt * K.inv_dx;
     a.dtdy = dt * K.inv_dy;
     const size_t n = (size_t)K.nx * K.ny;
-    a.wb = scratch;
-    a.y0b = a.wb + 36 * n;
-    a.sob = a.y0b + n;
-    a.colb = a.sob + n;
+    const size_t ntx = (K.nx + bn::kTX - 1) / bn::kTX, nty = (K.ny + bn::kTY - 1) / bn::kTY;
+    a.own = scratch;
+    a.ring = a.own + 4 * n;
+    a.colb = a.ring + ntx * nty * 4 * bn::kRing;
+    a.colt = a.colb + nty * K.nx;
     const unsigned gc = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((K.nx + bn::kTX - 1) / bn::kTX, (K.ny + bn::kTY - 1) / bn::kTY),
-                       dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64, (K.ny + bn::kColRows - 1) / bn::kColRows), dim3(64),
-                       0, stream, a);
+    hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((unsigned)ntx, (unsigned)nty), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

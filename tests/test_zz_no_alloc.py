@@ -57,7 +57,7 @@ def test_noalloc_adjoint_equals_the_allocating_one_on_two_calls(bn, torch_cuda):
 
 def test_noalloc_adjoint_rejects_a_grid_beyond_its_array(bn, torch_cuda):
     torch = torch_cuda
-    s = sc.dam_break_small(1024, 512)  # 38 planes of 524288 cells (19.9 M doubles) > 2^24
+    s = sc.dam_break_small(2048, 2048)  # 4 planes of 4194304 cells alone (16.8 M doubles) > 2^24
     with bn.Simulation(s) as sim:
         q = torch.from_numpy(np.ascontiguousarray(s.q)).cuda()
         out = torch.zeros_like(q)
