@@ -18,7 +18,7 @@
 //                         and of y0_i) and sum the stencil adjoints per target cell in LDS: the
 //                         tile's cells' sums (4 planes), those falling on the halo (140 cells per
 //                         tile) and the tile's share of each column's y0 adjoint
-//   2. adj_col_kernel     add the tiles' shares of each column's y0 adjoint in row order; and (if
+//   2. adj_col_kernel     add the tiles' shares of each column's y0 adjoint (fixed order); and (if
 //                         asked) the adjoint of each column's bottom height: its y0 adjoint times
 //                         dy0/dy_L = (alpha_l - alpha_first) / (alpha_l - alpha_g) (0 for a column
 //                         without fluid cells)
@@ -427,26 +427,26 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
             ((sr[4][t] + sr[4][kTX + t]) + sr[4][2 * kTX + t]) + sr[4][3 * kTX + t];
 }
 
-// The y0 adjoint of column i: the tiles' shares added in row order; and the adjoint of the column's
-// bottom height, its y0 adjoint times dy0/dy_L (0 for a column without fluid cells).
-__global__ __launch_bounds__(64) void adj_col_kernel(AdjArgs a)
+// The y0 adjoint of column i, one wavefront per column: lane l adds the shares of tile rows l,
+// l + 64, ... in order, then the lanes' sums are combined by a butterfly (every lane ends with the
+// same total: a fixed order, deterministic); and the adjoint of the column's bottom height, its y0
+// adjoint times dy0/dy_L (0 for a column without fluid cells).
+constexpr int kColWaves = 4;
+__global__ __launch_bounds__(64 * kColWaves) void adj_col_kernel(AdjArgs a)
 {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= a.K.nx) return;
+    const int lane = (int)threadIdx.x & 63;
+    const int i = (int)blockIdx.x * kColWaves + ((int)threadIdx.x >> 6);
+    if (i >= a.K.nx) return;  // a whole wavefront
     const int nty = (a.K.ny + kTY - 1) / kTY;
     const GlobalD cb = (GlobalD)a.colb;
     double col = 0.0;
-    int by = 0;
-    for (; by + 8 <= nty; by += 8) {
-        double v[8];
+    for (int by = lane; by < nty; by += 64) col += cb[(size_t)by * a.K.nx + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = cb[(size_t)(by + u) * a.K.nx + i];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) col += v[u];
+    for (int off = 32; off >= 1; off >>= 1) col += __shfl_xor(col, off);
+    if (lane == 0) {
+        a.colt[i] = col;
+        if (a.gbot) a.gbot[i] = a.jb[i] < a.K.ny ? col * first_gap(a, i) : 0.0;
     }
-    for (; by < nty; ++by) col += cb[(size_t)by * a.K.nx + i];
-    a.colt[i] = col;
-    if (a.gbot) a.gbot[i] = a.jb[i] < a.K.ny ? col * first_gap(a, i) : 0.0;
 }
 
 __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a)
@@ -533,7 +533,8 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.colt = a.colb + nty * K.nx;
     const unsigned gc = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((unsigned)ntx, (unsigned)nty), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + 63) / 64), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + bn::kColWaves - 1) / bn::kColWaves), dim3(64 * bn::kColWaves), 0,
+                       stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
