@@ -139,7 +139,7 @@ struct ArrayStencil {
 };
 
 // ---- pass 1: reconstruction, edges and cells, fused over 64 x 4 tiles ----------------------------
-// One workgroup (256 threads) per tile of 64 columns x 4 rows.  (a) It recomputes the reconstruction
+// One workgroup (a thread per cell) per tile of 64 columns x 4 rows.  (a) It recomputes the reconstruction
 // of the tile's cells and of a one-cell halo around it (66 x 6 cells) into LDS; (b) every x- and y-edge
 // touching a tile cell (65 x 4 and 64 x 5) is reversed from those records and the lambdas of its two
 // cells, the adjoints of the tile cells' edge states going back into LDS (over the records, after a
@@ -147,9 +147,12 @@ struct ArrayStencil {
 // target cell in LDS.  The edge-state records and their adjoints never reach HBM, nor do the
 // per-stencil-entry adjoints.
 constexpr int kTX = 64, kTY = 4, kHX = kTX + 2, kHY = kTY + 2, kHalo = kHX * kHY;  // 396 records
+constexpr int kThreads = kTX * kTY;  // one thread per tile cell
+static_assert((kTX + 1) * kTY <= 2 * kThreads && kTX * (kTY + 1) <= 2 * kThreads, "two rounds of edges");
 // the halo's 140 cells in ring order: the row below (66), the row above (66), the column left of the
 // tile's rows (4), the column right of them (4)
 constexpr int kRing = 2 * kHX + 2 * kTY;
+static_assert(kRing <= kThreads, "one ring cell per thread");
 __device__ __forceinline__ int ring_cell(int r)
 {
     if (r < kHX) return r;
@@ -258,9 +261,9 @@ __device__ __forceinline__ void fused_yedge(const AdjArgs &a, const double (*sr)
     qpb[4] = e1pb + (flB ? 0.0 : e1mb);
 }
 
-__global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
+__global__ __launch_bounds__(kThreads) void adj_fused_kernel(AdjArgs a)
 {
-    __shared__ double sr[kRecPlanes][kHalo];  // records, then (planes 0..17, first 256 entries) face adjoints
+    __shared__ double sr[kRecPlanes][kHalo];  // records, then (planes 0..17, first kThreads entries) face adjoints
     __shared__ double sy0[kHX];               // free-surface heights of the tile's columns and halo
     __shared__ int sf[kHalo];                 // flags of the tile's cells and halo
     const int t = threadIdx.x;
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     __syncthreads();
 
     // (a) records of the tile and its halo
-    for (int h = t; h < kHalo; h += 256) {
+    for (int h = t; h < kHalo; h += kThreads) {
         const int i = i0 + h % kHX - 1, j = j0 + h / kHX - 1;
         double wq[3][3][4];
         int wf[3][3];
@@ -294,16 +297,17 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     }
     __syncthreads();
 
-    // (b) edges: thread t takes x-edges t and t + 256 (of 65 x 4) and y-edges t and t + 256 (of 64 x 5)
+    // (b) edges: thread t takes x-edges t and t + kThreads (of 65 x 4) and y-edges t and t + kThreads
+    // (of 64 x 5)
     constexpr int nX = (kTX + 1) * kTY, nY = kTX * (kTY + 1);
     double xm[2][4], xp[2][4], ym[2][5], yp[2][5];
     bool xl[2], xr[2], yb[2], yt[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const int ex = t + 256 * u;
+        const int ex = t + kThreads * u;
         xl[u] = xr[u] = false;
         if (ex < nX) fused_xedge(a, sr, sf, i0, j0, ex % (kTX + 1), ex / (kTX + 1), xm[u], xp[u], xl[u], xr[u]);
-        const int ey = t + 256 * u;
+        const int ey = t + kThreads * u;
         yb[u] = yt[u] = false;
         if (ey < nY) fused_yedge(a, sr, sf, i0, j0, ey % kTX, ey / kTX, ym[u], yp[u], yb[u], yt[u]);
     }
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     // fluid is skipped (a missing side's share is already in its fluid neighbour's)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const int ex = t + 256 * u;
+        const int ex = t + kThreads * u;
         if (ex < nX) {
             const int e = ex % (kTX + 1), ty = ex / (kTX + 1);
             if (xl[u] && e >= 1) {
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
                 for (int k = 0; k < 4; ++k) sr[P_QW + k][ty * kTX + e] = xp[u][k];
             }
         }
-        const int ey = t + 256 * u;
+        const int ey = t + kThreads * u;
         if (ey < nY) {
             const int tx = ey % kTX, e = ey / kTX;
             if (yb[u] && e >= 1) {
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
     // one stencil entry after another: within one entry the targets of different cells differ, so
     // every sum is taken in the fixed order of the entries (deterministic).  A first-order cell
     // reaches only itself.  The y0 adjoints of the tile's cells go to plane 4.
-    for (int h = t; h < kHalo; h += 256) {
+    for (int h = t; h < kHalo; h += kThreads) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) sr[k][h] = 0.0;
     }
@@ -422,9 +426,12 @@ __global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs a)
         for (int k = 0; k < 4; ++k) a.ring[(tile * 4 + k) * kRing + t] = sr[k][h];
     }
     // the tile's share of each column's y0 adjoint (its rows in order; rows off the grid hold 0)
-    if (t < kTX && i0 + t < a.K.nx)
-        a.colb[(size_t)blockIdx.y * a.K.nx + i0 + t] =
-            ((sr[4][t] + sr[4][kTX + t]) + sr[4][2 * kTX + t]) + sr[4][3 * kTX + t];
+    if (t < kTX && i0 + t < a.K.nx) {
+        double cs = sr[4][t];
+#pragma unroll
+        for (int r = 1; r < kTY; ++r) cs += sr[4][r * kTX + t];
+        a.colb[(size_t)blockIdx.y * a.K.nx + i0 + t] = cs;
+    }
 }
 
 // The y0 adjoint of column i, one wavefront per column: lane l adds the shares of tile rows l,
@@ -532,7 +539,7 @@ hipError_t bn_adjoint_launch(const bn::Consts &K, const double *q, const double 
     a.colb = a.ring + ntx * nty * 4 * bn::kRing;
     a.colt = a.colb + nty * K.nx;
     const unsigned gc = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((unsigned)ntx, (unsigned)nty), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(bn::adj_fused_kernel, dim3((unsigned)ntx, (unsigned)nty), dim3(bn::kThreads), 0, stream, a);
     hipLaunchKernelGGL(bn::adj_col_kernel, dim3((K.nx + bn::kColWaves - 1) / bn::kColWaves), dim3(64 * bn::kColWaves), 0,
                        stream, a);
     hipLaunchKernelGGL(bn::adj_gather_kernel, dim3(gc), dim3(256), 0, stream, a);
