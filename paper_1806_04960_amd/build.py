@@ -1,5 +1,7 @@
-"""Build the HIP library ``libbn2d.so`` for gfx950 (in-tree, so it travels with the sources), and
-the attainable-peak probes ``libbn2d_probe.so`` that ``bench.py`` uses for the roofline."""
+"""Build the HIP library ``libbn2d.so`` for gfx950 (in-tree, so it travels with the sources), the
+attainable-peak probes ``libbn2d_probe.so`` that ``bench.py`` uses for the roofline, and
+``libbn2d_timeline.so``, the library with the step kernel's per-wavefront timeline compiled in
+(``python -m paper_1806_04960_amd.timeline``)."""
 import os
 import subprocess
 
@@ -9,6 +11,8 @@ LIB = os.path.join(HERE, "libbn2d.so")
 # attainable-peak probes for the roofline (measurement only)
 PROBE_SRC = [os.path.join(HERE, "csrc", "bn2d_probe.hip")]
 PROBE_LIB = os.path.join(HERE, "libbn2d_probe.so")
+# the same library with the step kernel's per-wavefront timeline compiled in (measurement only)
+TIMELINE_LIB = os.path.join(HERE, "libbn2d_timeline.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -18,9 +22,9 @@ FLAGS = [
 ]
 
 
-def _compile(srcs, lib, verbose):
+def _compile(srcs, lib, verbose, extra=()):
     tmp = lib + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -30,6 +34,7 @@ def _compile(srcs, lib, verbose):
 def build(verbose: bool = False) -> str:
     _compile(SRC, LIB, verbose)
     _compile(PROBE_SRC, PROBE_LIB, verbose)
+    _compile(SRC, TIMELINE_LIB, verbose, ["-DBN2D_TIMELINE"])
     return LIB
 
 

@@ -647,6 +647,19 @@ __device__ __forceinline__ StripInfo strip_at(unsigned long long ca, int g)
     return *(const StripInfo *)(StripPtr)addr;
 }
 
+#ifdef BN2D_TIMELINE
+// Opt-in instrumentation, compiled only with -DBN2D_TIMELINE (the library libbn2d_timeline.so, never
+// the default one): per wavefront w, record w of g_timeline holds the real-time clock (100 MHz) at
+// entry, after the strip totals, after the strip's table entry, after its row costs, after locating
+// its range, after its own range and at exit, then its own range (strip, first row, rows) and the
+// number of ranges it stole; bn_timeline_read copies the records of the last step to the host.
+constexpr int kTimelineWaves = 16384, kTimelineWords = 16;
+__device__ unsigned long long g_timeline[kTimelineWaves * kTimelineWords];
+#define BN_TIMELINE(...) __VA_ARGS__
+#else
+#define BN_TIMELINE(...)
+#endif
+
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
 {
     __shared__ double sq[3][4][64];
@@ -654,6 +667,8 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
 
     const int lane = threadIdx.x, w = blockIdx.x;
     const unsigned long long ma = a.maddr, ca = a.caddr;
+    BN_TIMELINE(unsigned long long tl[7] = {__builtin_amdgcn_s_memrealtime(), 0, 0, 0, 0, 0, 0};
+                long long tl_own[3] = {-1, 0, 0}; long long tl_steals = 0;)
     int nm, P;
     {
         const Control &C = control_at(ca);
@@ -685,6 +700,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
         const Control &C = control_at(ca);
         Chunks<double> strips;
         strips.load(C.Ts_in, C.nstrips);
+        BN_TIMELINE(tl[1] = __builtin_amdgcn_s_memrealtime() + (unsigned long long)(strips.total != strips.total);)
         const double step = strips.total / P;
         // (the last share ends beyond every strip: its end is not compared against the total)
         int g_w, g_next;
@@ -693,8 +709,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
         strips.find(w + 1 < P ? (w + 1) * step : 1e300, g_next, soff1);
         if (g_w < C.nstrips) {
             const StripInfo si = strip_at(ca, g_w);
+            BN_TIMELINE(tl[2] = __builtin_amdgcn_s_memrealtime() + (unsigned long long)(si.ny < 0);)
             Chunks<float> rows;
             rows.load(C.cost_in + si.cost_base, si.ny);
+            BN_TIMELINE(tl[3] = __builtin_amdgcn_s_memrealtime() + (unsigned long long)(rows.total != rows.total);)
             int lo, hi;
             double roff;
             rows.find(soff0, lo, roff);
@@ -707,6 +725,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
                 g = g_w;
                 j0 = lo;
                 E = min(lo + a.B, hi);
+                BN_TIMELINE(tl_own[0] = g_w; tl_own[1] = lo; tl_own[2] = hi - lo;)
             }
             // strips the share spans whole are left unowned (a strip cheaper than a share), counted
             // first: thieves scan every descriptor while the count is positive
@@ -725,8 +744,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
 
     // own range, then the owned head of the next strip, then whatever can be taken (one call site
     // of the march, so that its code exists once)
+    BN_TIMELINE(tl[4] = __builtin_amdgcn_s_memrealtime();)
     for (int phase = 0;; ++phase) {
         if (phase == 1) {
+            BN_TIMELINE(tl[5] = __builtin_amdgcn_s_memrealtime();)
             have = false;
             if (head_g >= 0) {
                 const Control &C = control_at(ca);
@@ -749,12 +770,24 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs a)
         } else if (phase >= 2) {
             have = steal(ca, a.B, &g, &j0, &E, &slot);
             if (!have) break;
+            BN_TIMELINE(++tl_steals;)
         }
         if (have) {
             const StripInfo si = strip_at(ca, g);
             march(a, ma, ca, sq, sf, si.member, g, si.local, j0, E, slot);
         }
     }
+#ifdef BN2D_TIMELINE
+    tl[6] = __builtin_amdgcn_s_memrealtime();
+    if (lane == 0 && w < kTimelineWaves) {
+        unsigned long long *T = g_timeline + (size_t)w * kTimelineWords;
+        for (int k = 0; k < 7; ++k) T[k] = tl[k];
+        T[7] = (unsigned long long)tl_own[0];
+        T[8] = (unsigned long long)tl_own[1];
+        T[9] = (unsigned long long)tl_own[2];
+        T[10] = (unsigned long long)tl_steals;
+    }
+#endif
 }
 
 // Fixed-point free-surface integral and CFL rate of a state given through bn_set_state (thread =
@@ -865,3 +898,14 @@ __global__ void y0_kernel(const long long *S, const int *jb, const double *dbot,
 }
 
 }  // namespace bn
+
+#ifdef BN2D_TIMELINE
+// The instrumented build's records of the last step: `waves` records of 16 words (the layout above)
+// into the caller's host buffer.  0, or -2 on a HIP error.  Exists only in libbn2d_timeline.so.
+extern "C" int bn_timeline_read(unsigned long long *host, int waves)
+{
+    if (!host || waves < 0 || waves > bn::kTimelineWaves) return -1;
+    return hipMemcpyFromSymbol(host, HIP_SYMBOL(bn::g_timeline),
+                               sizeof(unsigned long long) * bn::kTimelineWords * (size_t)waves) == hipSuccess ? 0 : -2;
+}
+#endif
