@@ -5,7 +5,7 @@ After ``--warmup`` steps of a workload, each of ``--steps`` single steps is trac
 real-time clock (100 MHz) at entry, after the strip totals, after its strip's table entry, after its
 row costs, after locating its range, after its own range and at exit, its own range and its steals.
 Printed per traced step (microseconds from the first wavefront's entry): medians and percentiles of
-those points, the own ranges' rows and durations, the latest own ranges, and the median end of the
+those points, the own ranges' rows and durations, the latest own ranges and exits, and the median end of the
 own ranges per wavefront residue mod 8 (workgroups are dealt to the 8 XCDs in turn).  The
 instrumentation adds its clock reads and one record store per wavefront, so its launches run a few
 percent longer than the default library's.
@@ -48,6 +48,8 @@ def summarise(rec):
     dur = [(r[5] - r[4]) * TICK_US for r in own]
     latest = sorted(((us(r[5]), w, int(r[7]), int(r[8]), int(r[8]) + int(r[9])) for w, r in enumerate(rec) if r[9] > 0),
                     reverse=True)[:8]
+    last_exits = sorted(((us(r[6]), us(r[5]) if r[5] else None, w, int(r[10])) for w, r in enumerate(rec)),
+                        reverse=True)[:8]
     by_xcd = [statistics.median([own_end[w] for w in range(x, len(rec), 8)]) for x in range(8)]
     pct = lambda v: {"median": statistics.median(v), "p90": quantile(v, 0.9), "p99": quantile(v, 0.99), "max": max(v)}
     return {
@@ -62,6 +64,7 @@ def summarise(rec):
         "own_range_duration": pct(dur),
         "steals_total": int(sum(r[10] for r in rec)),
         "latest_own_ranges": [{"end": e, "wavefront": w, "strip": g, "rows": [a, b]} for e, w, g, a, b in latest],
+        "latest_exits": [{"exit": e, "own_range_end": o, "wavefront": w, "steals": n} for e, o, w, n in last_exits],
         "own_range_end_median_by_wavefront_mod_8": by_xcd,
     }
 
