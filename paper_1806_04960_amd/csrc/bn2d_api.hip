@@ -303,6 +303,7 @@ int launch_step(bn_batch *b, bool cfl_dt, double dt_arg)
     a.cur = b->cur;
     a.m3 = b->m3;
     a.B = b->B;
+    a.cost_floor = b->nrows >= (long long)bn::kCostFloorRows * b->P ? bn::kCostFloor : 0.0;
     hipLaunchKernelGGL(bn::step_kernel, dim3(b->P), dim3(64), 0, b->stream, a);
     HIP_TRY(hipGetLastError());
     b->cur ^= 1;

@@ -64,6 +64,16 @@ struct StepArgs {
     int cur;                        // current state buffer
     int m3;                         // rotation of the 3-way buffers
     int B;                          // rows per claim
+    double cost_floor;              // least recorded row cost, as a fraction of its strip's mean
+                                    // row cost in the previous step (0: none)
 };
+
+// The cost floor where the wavefronts' shares average at least kCostFloorRows rows (rows measured
+// cheap still count for most of a typical row, so that no share packs many more rows than its
+// strip's average; 0.90 changes nothing on the 2048 x 1024 dam break, 0.95 and above slow the 4096^2
+// drop and the ensemble, whose gas rows stay cheap; with a few rows a share, as on a 512 x 256 grid,
+// any floor slows the step).
+constexpr double kCostFloor = 0.92;
+constexpr int kCostFloorRows = 8;
 
 }  // namespace bn

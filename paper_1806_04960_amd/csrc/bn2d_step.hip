@@ -73,6 +73,7 @@ __device__ __forceinline__ const Control &control_at(unsigned long long addr)
 // Range descriptor: one 64-bit word, [63] owned, [62:48] strip, [47:24] end row (exclusive),
 // [23:0] next unclaimed row.  The owner claims with an atomic add of B; a thief lowers the end.
 constexpr unsigned long long kOwned = 1ull << 63;
+
 __host__ __device__ inline int d_cur(unsigned long long d) { return (int)(d & 0xFFFFFFull); }
 __host__ __device__ inline int d_end(unsigned long long d) { return (int)((d >> 24) & 0xFFFFFFull); }
 __host__ __device__ inline int d_strip(unsigned long long d) { return (int)((d >> 48) & 0x7FFFull); }
@@ -315,6 +316,9 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
     bool outstanding = false, last = slot < 0;
     const long long t_begin = clock64();
     unsigned long long claim = 0;
+    // the least cost to record a row at (loaded now: at the range's end the recording would wait
+    // for it)
+    const double floor_cost = a.cost_floor > 0.0 ? a.cost_floor * (control_at(ca).Ts_in[g] / ny) : 0.0;
 
     // pending row (below the row being reconstructed): its update with every term but its north
     // edge's D-, and its north edge state
@@ -502,11 +506,14 @@ __device__ void march(const StepArgs &a, unsigned long long ma, unsigned long lo
         }
     }
 
-    // recorded cost of the rows marched here, for the next step's partition
+    // recorded cost of the rows marched here, for the next step's partition: the range's time
+    // spread evenly over its rows, but at least a.cost_floor of the strip's mean row cost of this
+    // step's partition (rows recorded cheap are where a share packs the most rows, and where a
+    // change of the flow since, a liquid front arriving, makes the share late)
     const Control &C = control_at(ca);
     const long long cbase = member_ref(mab).cost0 + (long long)strip * ny;  // (the strip's cost_base)
-    const double spent = (double)(clock64() - t_begin);
-    const float per_row = (float)(spent / (E - j0));
+    const float per_row = (float)fmax((double)(clock64() - t_begin) / (E - j0), floor_cost);
+    const double spent = (double)per_row * (E - j0);
     for (int rr = j0 + lane; rr < E; rr += 64) C.cost_out[cbase + rr] = per_row;
     if (lane == 0) atomicAdd(&C.Ts_out[g], spent);
 }
