@@ -534,8 +534,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would own a strip "
-              "of columns; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would own a strip "
+              "of columns and exchange two halo columns a side per step). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

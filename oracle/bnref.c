@@ -14,7 +14,7 @@
  * the same source builds a single-threaded oracle.)
  *
  * Where the paper is silent, ambiguous or garbled the oracle takes one reading; each reading
- * is tagged [Rn] where it is used and listed with its justification in the design notes.
+ * is tagged [Rn] where it is used and listed below with its justification.
  *
  *  [R1]  The cell integral of the scheme is taken of the full system matrix A = dF/dQ + B
  *        (Sec. 3, eq. "Scheme" together with the path-conservative form it cites): the cell's
