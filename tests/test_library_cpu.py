@@ -27,6 +27,22 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_timeline_instrumentation_only_in_its_own_build():
+    """The step kernel's per-wavefront timeline (BN2D_TIMELINE) is compiled into
+    libbn2d_timeline.so alone: the default library neither exports its reader nor differs in ABI."""
+    L = bn2d.lib()
+    assert not hasattr(L, "bn_timeline_read")
+    path = os.path.join(ROOT, "paper_1806_04960_amd", "libbn2d_timeline.so")
+    if not os.path.exists(path):
+        pytest.skip("libbn2d_timeline.so not built")
+    T = ctypes.CDLL(path)
+    assert hasattr(T, "bn_timeline_read")
+    for name in declared_symbols():
+        assert hasattr(T, name), name
+    T.bn_timeline_read.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert T.bn_timeline_read(None, 1) == -1  # rejected before any HIP call
+
+
 def test_binding_declares_every_signature():
     """Every entry point has its ctypes argument types (a call without them fails on a double
     argument), with as many arguments as the header's prototype."""
